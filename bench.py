@@ -1,0 +1,233 @@
+#!/usr/bin/env python
+"""Benchmark of the splat-and-trace path on one MI355X.
+
+A step is one pass of the whole path over one frame of synthetic input:
+SPH particles -> delta-n grid with its gradient (cell list, splat gather,
+gradient/pack) -> every pixel of every view traced through the field (ray
+generation, adaptive march, backdrop displacement).  Inputs are resident in
+HBM before the timed region starts.
+
+Workload (default): 262,144 particles in a 1 x 1 x 2 m box (main plume + 3
+seeded plumes), 128^3 FP32 grid, one 1280x720 view, adaptive step with
+theta_max = 0.003 and h_max = 1 voxel; the fixed-step trace (0.25 voxel) is
+timed the same way for the adaptive-vs-uniform comparison.
+
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 is refused: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/s & ray-steps/s, adaptive vs uniform step, 1 MI355X; p50/p99 view latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_STEP = {"f32": 128, "f16": 64, "bf16": 64}   # 8 corners x 4 channels
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=()):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ctx.profile_read("march", reset=True)
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile_enable(False)
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    kt = {k: ctx.profile_read(k) for k in kernels}
+    ctx.profile_read("march", reset=True)
+    return (t1 - t0) * 1e3 / steps, per, kt
+
+
+def count_pairs(torch, parts, grid, h: float) -> int:
+    """(voxel, particle) pairs closer than 2h: the splat's algorithmic work units."""
+    R = 2.0 * h
+    lo = torch.tensor(np.asarray(grid.lo, np.float64), device="cuda")
+    sp = torch.tensor(np.asarray(grid.spacing, np.float64), device="cuda")
+    res = torch.tensor(np.asarray(grid.res, np.int64), device="cuda")
+    p = torch.stack([parts.x, parts.y, parts.z], 1).double()
+    base = torch.floor((p - lo) / sp - 0.5).long()
+    r = [int(math.ceil(R / float(s))) + 1 for s in grid.spacing]
+    total = 0
+    for dk in range(-r[2], r[2] + 2):
+        for dj in range(-r[1], r[1] + 2):
+            off = torch.tensor([0, dj, dk], device="cuda")
+            for di in range(-r[0], r[0] + 2):
+                off[0] = di
+                v = base + off
+                inside = ((v >= 0) & (v < res)).all(1)
+                c = lo + (v.double() + 0.5) * sp
+                d2 = ((c - p) ** 2).sum(1)
+                total += int(((d2 < R * R) & inside).sum())
+    return total
+
+
+def cpu_baseline(wl, args) -> dict:
+    """The FP64 oracle on the host cores: full splat + a bounded ray sample."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    md = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h, "cells")
+    t_splat = time.perf_counter() - t0
+    rng = np.random.default_rng(12345)
+    ns = min(wl.nrays, args.cpu_rays)
+    ids = np.sort(rng.choice(wl.nrays, size=ns, replace=False)).astype(np.int64)
+    t0 = time.perf_counter()
+    r = oracle.trace_views(md, wl.views, wl.step_adaptive, ray_ids=ids)
+    t_trace = time.perf_counter() - t0
+    frame_s = t_splat + t_trace * wl.nrays / ns
+    return {"value": wl.nrays / frame_s, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle: full splat of the {tuple(int(x) for x in wl.grid.res)} grid "
+                       f"({t_splat:.2f} s) + {ns} random rays of the {wl.nrays}-ray frame, adaptive "
+                       f"({t_trace:.2f} s), scaled to one frame"),
+            "ray_steps_per_s": float(r["steps"].sum()) / t_trace, "frame_s": frame_s}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--theta", type=float, default=None, help="override theta_max of the adaptive step")
+    ap.add_argument("--cpu-rays", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true")
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              f"the path shards by views/pixel tiles with the field replicated, see the design notes",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2603_02048_amd import haze
+    from paper_2603_02048_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 3
+    torch.cuda.set_device(0)
+    wl = W.make_config(args.config)
+    st_a, st_u = wl.step_adaptive, wl.step_uniform
+    if args.theta is not None:
+        st_a, _ = W.make_steps(wl.grid, theta_max=args.theta)
+    scale = 1e4 if args.dtype != "f32" else 1.0
+    log(f"bench: {wl.name} particles={wl.particles.n} grid={tuple(int(r) for r in wl.grid.res)} "
+        f"views={len(wl.views)} rays={wl.nrays} dtype={args.dtype}")
+
+    ctx = haze.Context(0)
+    parts = haze.upload_particles(wl.particles)
+    out = haze.alloc_outputs(wl.nrays)
+    nrays = wl.nrays
+
+    def make_step(st):
+        def fn():
+            f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype=args.dtype, store_scale=scale)
+            ctx.trace_views(f, wl.views, st, out=out)
+            f.release()
+        return fn
+
+    kernels = ("cell_list", "splat_gather", "grad_pack", "raygen", "march")
+    res = {}
+    for name, st in (("adaptive", st_a), ("uniform", st_u)):
+        ms, per, kt = time_steps(ctx, torch, make_step(st), args.steps, args.warmup, kernels)
+        steps_total = int(out["steps"].sum().item())
+        hits = int((out["steps"] > 0).sum().item())
+        res[name] = dict(ms=ms, per=per, kt=kt, steps=steps_total, hits=hits)
+        log(f"bench: {name}: {ms:.3f} ms/step (p50 {np.percentile(per, 50):.3f}, p99 {np.percentile(per, 99):.3f}), "
+            f"ray-steps {steps_total}, rays in volume {hits}; kernels " +
+            ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in kt.items()))
+
+    A, U = res["adaptive"], res["uniform"]
+    rays_s = nrays / (A["ms"] * 1e-3)
+    # dominant kernel of the adaptive step
+    avg = {k: v[0] / max(v[1], 1) for k, v in A["kt"].items()}
+    dominant = max(avg, key=avg.get)
+    roofline = None
+    march_ms = avg["march"]
+    march_gbs = A["steps"] * BYTES_PER_STEP[args.dtype] / (march_ms * 1e-3) / 1e9
+    if dominant == "march":
+        roofline = {"kernel": "k_march", "bound": "hbm", "achieved": march_gbs, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": march_gbs / HBM_PEAK_GBS, "traffic": None,
+                    "per_unit": f"{BYTES_PER_STEP[args.dtype]} B per ray-step (8 corners x 4 channels)"}
+    pairs = None
+    if not args.no_pairs:
+        pairs = count_pairs(torch, parts, wl.grid, wl.h)
+    if dominant == "splat_gather" and pairs is not None:
+        flops = pairs * 25.0
+        tf = flops / (avg["splat_gather"] * 1e-3) / 1e12
+        roofline = {"kernel": "k_splat", "bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
+                    "frac": tf / 78.6, "traffic": None,
+                    "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h"}
+
+    line = {
+        "metric": METRIC,
+        "value": rays_s,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": A["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": (f"{wl.name}: {wl.particles.n} SPH particles, "
+                                f"{'x'.join(str(int(r)) for r in wl.grid.res)} grid, {len(wl.views)} view(s) "
+                                f"{wl.views[0].width}x{wl.views[0].height}, splat + adaptive trace per step"),
+                   "theta_max": st_a.theta_max, "h_max_voxel": 1.0, "uniform_step_voxel": 0.25,
+                   "parallelism": "single GPU"},
+        "ray_steps_per_s": A["steps"] / (A["ms"] * 1e-3),
+        "latency_ms": {"p50": float(np.percentile(A["per"], 50)), "p99": float(np.percentile(A["per"], 99))},
+        "adaptive": {"rays_per_s": rays_s, "ray_steps": A["steps"], "rays_in_volume": A["hits"],
+                     "trace_rays_per_s": nrays / ((avg["raygen"] + avg["march"]) * 1e-3),
+                     "trace_ray_steps_per_s": A["steps"] / ((avg["raygen"] + avg["march"]) * 1e-3)},
+        "uniform": {"rays_per_s": nrays / (U["ms"] * 1e-3), "ms_per_step": U["ms"], "ray_steps": U["steps"],
+                    "ray_steps_per_s": U["steps"] / (U["ms"] * 1e-3),
+                    "latency_ms": {"p50": float(np.percentile(U["per"], 50)),
+                                   "p99": float(np.percentile(U["per"], 99))}},
+        "kernel_ms": {k: round(v, 5) for k, v in avg.items()},
+        "march_gather_GBps": march_gbs,
+        "splat_pairs": pairs,
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if pairs is not None:
+        line["splat_pairs_per_s"] = pairs / (avg["splat_gather"] * 1e-3)
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on the host (cpu_baseline)")
+        line["cpu_baseline"] = cpu_baseline(wl, args)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,283 @@
+/*
+ * haze.h -- C ABI of the MI355X (gfx950) splat-and-trace library `libhaze.so`.
+ *
+ * The library turns SPH particles into a refractive-index field and traces
+ * curved camera rays through it:
+ *
+ *   1. hz_splat_index_field: density at voxel centres by SPH kernel splatting,
+ *      mapped to the refractive-index excess delta_n = n - 1 = K_GD rho by the
+ *      Gladstone-Dale relation (paper Sec. 3.3.1, Eq. 12), and its gradient
+ *      grad n = K_GD grad rho by finite differences on the grid (Eq. 13).
+ *   2. hz_trace_views: per pixel of every view, a ray that is straight outside
+ *      the volume (Fig. 1 caption) and inside it follows the explicit update
+ *        omega_{k+1} = normalize(omega_k + ds_k/n_k (I - omega_k omega_k^T) g_k)
+ *        C_{k+1}     = C_k + ds_k omega_{k+1}                       (Eq. 16)
+ *      with n_k, g_k trilinearly sampled (Sec. 3.3.1) and the step
+ *        ds_k = clamp(n_k theta_max / (|(I - omega omega^T) g_k| + eps),
+ *                     ds_min, ds_max)                     (Eqs. 17-18)
+ *      or a fixed step (Sec. 4.1).  The image is formed only by bending
+ *      (Sec. 3.3.2, last paragraph): the exit ray is intersected with a
+ *      backdrop plane and re-projected through the same pinhole, giving a
+ *      per-pixel displacement.
+ *   3. hz_submit / hz_poll: the same trace as a request to a serving loop that
+ *      batches concurrent multi-view requests into shared launches.
+ *
+ * Conventions
+ *   - Lengths in metres, angles in radians, float32 unless stated.
+ *   - "device" pointers are HIP device memory on the context's GPU; "host"
+ *     pointers are ordinary process memory.  Structs passed by pointer are
+ *     host memory and are only read during the call.
+ *   - Grids are regular: voxel (i, j, k) has its centre at
+ *     lo + (i + 1/2, j + 1/2, k + 1/2) * (hi - lo) / res; exported arrays are
+ *     linear [z][y][x] (x fastest).
+ *   - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
+ *     stream) and the call returns without waiting for it.  Device faults show
+ *     up as HZ_E_DEVICE on a later call.
+ *   - Every call returns an hz_status; nothing throws or aborts across the
+ *     ABI.  On an error return no output has been written and no work queued.
+ *     hz_last_error() describes the most recent failure on the calling thread.
+ *   - A context is not thread-safe, except hz_submit and hz_poll, which may be
+ *     called from any thread.
+ */
+#ifndef HAZE_H
+#define HAZE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HZ_OK = 0,
+    HZ_PENDING = 1,         /* hz_poll: the request has not completed yet */
+    HZ_E_INVALID = -1,      /* bad argument (null pointer, size, range) */
+    HZ_E_NOMEM = -2,        /* the device allocator failed */
+    HZ_E_BUDGET = -3,       /* the request can never fit the context's HBM budget */
+    HZ_E_DEVICE = -4,       /* no usable GPU, or a HIP runtime/device error */
+    HZ_E_NOTFOUND = -5,     /* unknown ticket */
+    HZ_E_UNSUPPORTED = -6   /* valid but not supported by this build */
+} hz_status;
+
+/* Storage type of the index field.  Integration is always float32. */
+typedef enum {
+    HZ_F32 = 0,   /* 16 B per voxel: (delta_n, dn/dx, dn/dy, dn/dz) */
+    HZ_F16 = 1,   /* 8 B per voxel, each channel stored as half(value * store_scale) */
+    HZ_BF16 = 2   /* 8 B per voxel, each channel stored as bfloat16(value * store_scale) */
+} hz_dtype;
+
+/* Per-ray status codes written to hz_trace_out.status. */
+enum {
+    HZ_RAY_OK = 0,
+    HZ_RAY_MAXSTEPS = 1,    /* max_steps reached inside the volume */
+    HZ_RAY_NOHIT = 2,       /* exit ray misses the backdrop plane; disp is NaN */
+    HZ_RAY_NONFINITE = 3,   /* position or direction became non-finite */
+    HZ_RAY_BAD_ID = 4       /* ray_ids[i] is not a ray of the views; outputs are NaN */
+};
+
+typedef struct hz_ctx hz_ctx;       /* device, HBM ledger, scratch, serving loop */
+typedef struct hz_field hz_field;   /* device-resident (delta_n, grad n) grid, immutable */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the library itself allocates (fields, scratch, serving buffers);
+ * 0 means "free device memory at creation minus 1 GiB".
+ * Errors: HZ_E_INVALID (out == NULL), HZ_E_DEVICE (no such device / no GPU). */
+hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx **out);
+
+/* Wait for the context's outstanding work, release every field it still owns
+ * and free the context.  NULL is ignored. */
+void hz_ctx_destroy(hz_ctx *ctx);
+
+/* Message for the last failure on the calling thread ("" if none).  The
+ * string stays valid until the thread's next failing call. */
+const char *hz_last_error(void);
+
+/* Bytes of device memory the library currently holds for this context, and
+ * its budget. */
+hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* Per-kernel timing with HIP events recorded around every launch the context
+ * makes on the caller's stream (kernels: "cell_list", "splat_gather",
+ * "grad_pack", "raygen", "march").  hz_profile_read waits for the recorded
+ * events and returns the summed milliseconds and launch count of `kernel`
+ * since the last reset (reset != 0 clears all sums after reading). */
+hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);
+hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int32_t reset);
+
+/* ---------------------------------------------------------------------- */
+/* Index field (paper Sec. 3.3.1, Eqs. 12-13)                             */
+/* ---------------------------------------------------------------------- */
+
+/* Particle set, structure of arrays.  x, y, z, m are device pointers to n
+ * float32 values each (positions in metres, masses in kg), caller-owned and
+ * only read.  Particles farther than 2h from the grid box contribute nothing
+ * and are skipped. */
+typedef struct {
+    int64_t n;
+    const float *x, *y, *z, *m;
+} hz_particles;
+
+/* Regular grid over the box [lo, hi] with res[0] x res[1] x res[2] voxels. */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t res[3];
+} hz_grid;
+
+/* Splat parameters.  The kernel is the M4 cubic spline with smoothing length
+ * h (support 2h, normalisation 1/(pi h^3)).  store_scale multiplies every
+ * channel before it is stored as F16/BF16 (it is divided out when the tracer
+ * reads it); it must be 1 for F32. */
+typedef struct {
+    float k_gd;
+    float h;
+    hz_dtype dtype;
+    float store_scale;
+} hz_splat_params;
+
+/* Build the index field of a particle set:
+ *   delta_n(c) = k_gd * sum_j m_j W(|c - x_j|, h)  at every voxel centre c,
+ *   grad n     = second-order central differences inside the grid and
+ *                first-order one-sided differences on its faces.
+ * The sum over particles runs in a fixed order, so the field is bitwise
+ * identical across calls.  On success *out is a new field owned by the
+ * context (release it with hz_field_release).
+ * Errors: HZ_E_INVALID (null pointers, n < 1, res < 2 on an axis, hi <= lo,
+ * h <= 0, non-finite k_gd, store_scale <= 0 or != 1 for F32, more than
+ * 2^31 - 1 particles or voxels), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_splat_index_field(hz_ctx *ctx, const hz_particles *particles, const hz_grid *grid,
+                               const hz_splat_params *params, void *hip_stream, hz_field **out);
+
+/* Build the index field from a given delta_n grid: `dn` is a device array of
+ * res[0]*res[1]*res[2] float32 values, linear [z][y][x]; the gradient and the
+ * storage conversion are computed as in hz_splat_index_field.  For callers
+ * (and tests) that already have a density grid.
+ * Errors: as hz_splat_index_field. */
+hz_status hz_index_field_from_grid(hz_ctx *ctx, const float *dn, const hz_grid *grid, hz_dtype dtype,
+                                   float store_scale, void *hip_stream, hz_field **out);
+
+/* Export a field as four device arrays of res[0]*res[1]*res[2] float32 values,
+ * linear [z][y][x], decoded to physical units (any of them may be NULL).
+ * Errors: HZ_E_INVALID, HZ_E_DEVICE. */
+hz_status hz_field_read(hz_ctx *ctx, const hz_field *field, float *dn, float *gx, float *gy, float *gz,
+                        void *hip_stream);
+
+/* Grid and storage type of a field. */
+hz_status hz_field_info(const hz_field *field, hz_grid *grid, hz_dtype *dtype, float *store_scale,
+                        uint64_t *bytes);
+
+/* Release a field.  Does not block: the field's memory returns to the
+ * context's pool and is reused (by a later field of the same size) only by
+ * work ordered after every launch already queued that reads the field.
+ * Pooled memory stays charged to the budget until the context needs the room
+ * or is destroyed. */
+hz_status hz_field_release(hz_ctx *ctx, hz_field *field);
+
+/* ---------------------------------------------------------------------- */
+/* Curved-ray tracing (paper Sec. 3.3.2-3.3.3, Eqs. 15-18)                */
+/* ---------------------------------------------------------------------- */
+
+/* Pinhole camera with a backdrop plane.  fwd is the viewing direction, up
+ * fixes the roll (right = normalize(fwd x up)), vfov is the vertical field of
+ * view; pixel (p, q) has q = 0 at the top.  The backdrop is the plane through
+ * plane_p with unit normal plane_n facing the camera. */
+typedef struct {
+    float eye[3], fwd[3], up[3];
+    float vfov;
+    int32_t width, height;
+    float plane_p[3], plane_n[3];
+} hz_view;
+
+/* Step control.  uniform != 0 selects the fixed step ds_uniform; otherwise
+ * ds = clamp(n theta_max / (|(I - w w^T) g| + eps), ds_min, ds_max).  A step
+ * never runs past the volume: it is shortened to the exit distance along the
+ * current direction, and the march ends when that distance is <= tau_term or
+ * the new position is outside the volume, or after max_steps steps. */
+typedef struct {
+    int32_t uniform;
+    float theta_max, ds_min, ds_max, eps, ds_uniform;
+    int32_t max_steps;
+    float tau_term;
+} hz_step;
+
+/* Per-ray outputs, device arrays with one entry per traced ray:
+ *   disp      2 floats: displacement (px) of the scene point seen through the
+ *             volume from where the straight ray would see it, (+x right,
+ *             +y down); NaN when status is HZ_RAY_NOHIT
+ *   exit_pos  3 floats: where the ray leaves the volume (the eye for rays that
+ *             miss the volume)
+ *   exit_dir  3 floats: unit direction there
+ *   steps     number of update steps taken inside the volume
+ *   status    HZ_RAY_* code
+ * Any pointer may be NULL to skip that output. */
+typedef struct {
+    float *disp;
+    float *exit_pos;
+    float *exit_dir;
+    uint32_t *steps;
+    uint8_t *status;
+} hz_trace_out;
+
+/* Trace views[0..nviews) through `field` in one launch whose persistent waves
+ * share one queue of the rays of every view.  Rays are numbered by
+ * concatenating the views in order, each view row-major (ray id =
+ * offset_of_view + q * width + p).  If ray_ids (device, int64) is NULL all
+ * rays are traced and output i belongs to ray id i (nrays must equal the total
+ * pixel count); otherwise output i belongs to ray id ray_ids[i] for i <
+ * nrays.  `views` and `step` are host memory.  Results are bitwise identical
+ * across calls and launch shapes.
+ * Errors: HZ_E_INVALID (null ctx/field/views/step/out, nviews < 1 or > 4096,
+ * width/height < 1, vfov outside (0, pi), zero fwd or fwd parallel to up,
+ * zero plane_n, ds_min <= 0, ds_max < ds_min, theta_max <= 0, eps < 0,
+ * ds_uniform <= 0 with uniform set, max_steps < 1, tau_term < 0, nrays
+ * mismatch, more than 2^31 - 1 rays), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_trace_views(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                         const hz_step *step, const int64_t *ray_ids, int64_t nrays, const hz_trace_out *out,
+                         void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of multi-view requests                   */
+/* ---------------------------------------------------------------------- */
+
+typedef uint64_t hz_ticket;
+
+/* Start the context's serving loop: at most `slots` launches in flight at
+ * once (each on its own stream), each batching up to `max_batch_rays` rays of
+ * whole requests.  Requests are admitted while their output buffers and the
+ * launch scratch fit the HBM budget.  Errors: HZ_E_INVALID (slots < 1 or >
+ * 16, max_batch_rays < 1), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_server_start(hz_ctx *ctx, int32_t slots, int64_t max_batch_rays);
+
+/* Submit a request: trace all pixels of views[0..nviews) through `field` with
+ * `step`.  Non-blocking; views and step are copied.  The library allocates
+ * the request's outputs (see hz_request_outputs); `field` must stay alive
+ * until the request completes.  Requests that arrive while others run join
+ * the next launch whose slot and memory are free; requests for different
+ * fields of the same grid and storage type share launches.
+ * Errors: HZ_E_INVALID (as hz_trace_views, or no server), HZ_E_BUDGET (the
+ * request alone exceeds the budget or a batch). */
+hz_status hz_submit(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                    const hz_step *step, hz_ticket *out);
+
+/* Poll a request: HZ_PENDING until its results are complete on the device,
+ * then HZ_OK with *latency_s = seconds from submit to completion (may be
+ * NULL).  Errors: HZ_E_NOTFOUND (unknown or already released ticket),
+ * HZ_E_DEVICE. */
+hz_status hz_poll(hz_ctx *ctx, hz_ticket ticket, double *latency_s);
+
+/* Device output arrays of a completed request (layout as hz_trace_views with
+ * ray_ids == NULL); valid until hz_request_release.  *nrays gets the number
+ * of rays.  Errors: HZ_E_NOTFOUND, HZ_E_INVALID (not complete yet). */
+hz_status hz_request_outputs(hz_ctx *ctx, hz_ticket ticket, hz_trace_out *out, int64_t *nrays);
+
+/* Free a completed request's outputs and forget its ticket. */
+hz_status hz_request_release(hz_ctx *ctx, hz_ticket ticket);
+
+/* Stop the serving loop after the requests already admitted have finished;
+ * pending requests are completed first. */
+hz_status hz_server_stop(hz_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAZE_H */

@@ -198,6 +198,11 @@ class Medium:
             m.dn, m.gx, m.gy, m.gz = [a.ctypes.data for a in self._keep]
         self._m = m
 
+    @property
+    def arrays(self):
+        """(dn, gx, gy, gz) of a gridded medium, [z][y][x] float64."""
+        return tuple(self._keep) if self._keep is not None else None
+
     @classmethod
     def from_grid(cls, grid, dn, gx=None, gy=None, gz=None):
         if gx is None:

@@ -1,0 +1,109 @@
+// haze_device.h -- structures shared by the gfx950 kernels and the host runtime
+// of libhaze.so (internal; the public ABI is include/haze.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace haze {
+
+// ---------------------------------------------------------------------------
+// splat: particle cell list and brick gather
+// ---------------------------------------------------------------------------
+
+// Cell list over the grid box grown by the kernel support 2h on every side.
+// Cells are cubes of edge `cell`; cell (cx, cy, cz) spans
+// clo + (cx, cy, cz) * cell.  Particles outside the grown box are not binned.
+struct CellGrid {
+    float clo[3];
+    float cell;
+    float inv_cell;
+    int32_t nc[3];
+    int32_t ncells;
+};
+
+// Geometry and constants of one splat launch.
+struct SplatParams {
+    float lo[3];          // grid box corner
+    float sp[3];          // voxel spacing
+    int32_t res[3];
+    int32_t nbx, nby, nbz; // bricks of 4x4x4 voxels per axis
+    float h;
+    float inv_h;
+    float support2;       // (2h)^2
+    float scale;          // k_gd / (pi h^3)
+    CellGrid cg;
+};
+
+// ---------------------------------------------------------------------------
+// trace: launch-uniform grid/step data and per-view jobs
+// ---------------------------------------------------------------------------
+
+// One view of one request.  Everything a ray of this view needs besides the
+// launch-uniform grid and step data.  Host code fills it; 16-byte aligned.
+struct alignas(16) TraceJob {
+    float eye[3];
+    float fpx;            // focal length in pixels: (H/2) / tan(vfov/2)
+    float f[3];           // unit forward
+    float half_w;         // W/2
+    float r[3];           // unit right = normalize(f x up)
+    float half_h;         // H/2
+    float u[3];           // unit up = r x f
+    int32_t width;
+    float plane_p[3];
+    int32_t height;
+    float plane_n[3];
+    int32_t tiles_x;      // 8x8 pixel tiles per row
+    const void *field;    // packed (delta_n, grad) voxels of this view's field
+    int64_t slot_begin;   // first queue slot (8x8 tile order) of this view
+    int64_t ray_begin;    // first global ray id (row-major order) of this view
+    float *disp;          // outputs of this view, indexed q * width + p
+    float *exit_pos;
+    float *exit_dir;
+    uint32_t *steps;
+    uint8_t *status;
+    int64_t pad_;
+};
+
+struct TraceGrid {
+    float lo[3], hi[3];
+    float inv_sp[3];       // 1 / spacing
+    float off[3];          // -lo / spacing - 1/2  (u = x * inv_sp + off)
+    float maxi[3];         // res - 2 (largest cell index) as float
+    int32_t res[3];
+    float inv_scale;       // 1 / store_scale
+};
+
+struct TraceStep {
+    int32_t uniform;
+    float theta_max, ds_min, ds_max, eps, ds_uniform, tau;
+    int32_t max_steps;
+    float near_cap;        // a point closer than this to a face may need the exit clamp
+};
+
+struct TraceOutFlat {      // outputs indexed by queue position (ray-subset mode)
+    float *disp;
+    float *exit_pos;
+    float *exit_dir;
+    uint32_t *steps;
+    uint8_t *status;
+};
+
+struct TraceLaunch {
+    const TraceJob *jobs;
+    int32_t njobs;
+    int32_t subset;        // 1: slots are positions in ray_ids; 0: 8x8 tile order over jobs
+    int64_t nslots;
+    const int64_t *ray_ids;
+    TraceOutFlat flat;
+    uint32_t *hits;        // compacted slots whose rays enter the volume
+    uint32_t *counters;    // [0] hit count, [1] march queue head
+    TraceGrid grid;
+    TraceStep step;
+    int32_t refill_min;    // refill a wave once this many lanes are idle
+};
+
+// Field storage types (match hz_dtype).
+enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
+
+}  // namespace haze

@@ -1,0 +1,866 @@
+// runtime.hip -- host side of libhaze.so: the C ABI of include/haze.h.
+//
+// Owns the context (device, HBM ledger, scratch), field objects, argument
+// validation, per-view job tables and the launches of splat.hip / trace.hip.
+// Every entry point validates its arguments before touching the device, so an
+// error return leaves outputs untouched and queues no work.
+#include "haze.h"
+#include "haze_device.h"
+#include "serve.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace haze {
+hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
+                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, hipStream_t);
+hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t);
+hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t);
+hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
+hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
+hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t);
+int march_blocks_per_cu(int);
+}  // namespace haze
+
+using namespace haze;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static hz_status fail(hz_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+static hz_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? HZ_E_NOMEM : HZ_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HZ_HIP(call, what)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, what);    \
+    } while (0)
+
+extern "C" const char *hz_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// context, ledger and scratch
+// ---------------------------------------------------------------------------
+
+// A device buffer reused across calls.  `last_use` orders a reuse on another
+// stream after the previous user's work.
+struct Scratch {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t last_use = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+};
+
+struct PinnedSlot {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+struct hz_field {
+    hz_ctx *ctx = nullptr;
+    void *data = nullptr;
+    uint64_t bytes = 0;
+    hz_grid grid{};
+    hz_dtype dtype = HZ_F32;
+    float store_scale = 1.0f;
+    hipEvent_t last_use = nullptr;
+    bool used = false;
+    std::mutex mu;
+};
+
+struct hz_ctx {
+    int device = 0;
+    int num_cus = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::mutex ledger_mu;
+    // splat scratch
+    Scratch cid, count, start, cursor, slots, sorted, dn;
+    // trace scratch
+    Scratch jobs, hits, counters;
+    std::vector<PinnedSlot> pinned;
+    size_t pinned_next = 0;
+    int march_bpc[3] = {0, 0, 0};
+    std::vector<hz_field *> fields;
+    std::mutex fields_mu;
+    // memory of released fields, reused in stream order (no host sync)
+    struct PoolBlock {
+        void *ptr;
+        size_t bytes;
+        hipEvent_t ready;   // recorded after the block's last use
+    };
+    std::vector<PoolBlock> pool;
+    std::mutex pool_mu;
+    // optional per-kernel event timing
+    struct ProfRec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    bool prof_on = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_free;
+    std::map<std::string, std::pair<double, int64_t>> prof_acc;
+    std::mutex prof_mu;
+    Server *server = nullptr;
+};
+
+static bool ledger_take(hz_ctx *c, uint64_t bytes)
+{
+    std::lock_guard<std::mutex> g(c->ledger_mu);
+    if (c->used.load() + bytes > c->budget) return false;
+    c->used += bytes;
+    return true;
+}
+
+static void ledger_give(hz_ctx *c, uint64_t bytes)
+{
+    std::lock_guard<std::mutex> g(c->ledger_mu);
+    c->used -= std::min<uint64_t>(bytes, c->used.load());
+}
+
+namespace haze {
+// Device allocation charged to the context's budget (used by serve.hip too).
+hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes)
+{
+    if (!ledger_take(c, bytes))
+        return fail(HZ_E_BUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu bytes in use)", bytes,
+                    (unsigned long long)c->used.load(), (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(p, bytes == 0 ? 256 : bytes);
+    if (e != hipSuccess) {
+        ledger_give(c, bytes);
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    return HZ_OK;
+}
+
+void ctx_free(hz_ctx *c, void *p, size_t bytes)
+{
+    if (p) (void)hipFree(p);
+    ledger_give(c, bytes);
+}
+
+int ctx_device(const hz_ctx *c) { return c->device; }
+int ctx_num_cus(const hz_ctx *c) { return c->num_cus; }
+}  // namespace haze
+
+// Make `s` at least `bytes` large and order its use on `stream` after its
+// previous use.  Growing waits for the previous user before freeing.
+static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_t stream)
+{
+    if (!s.last_use) HZ_HIP(hipEventCreateWithFlags(&s.last_use, hipEventDisableTiming), "hipEventCreate");
+    if (s.cap < bytes) {
+        if (s.used) HZ_HIP(hipEventSynchronize(s.last_use), "hipEventSynchronize");
+        if (s.ptr) {
+            ctx_free(c, s.ptr, s.cap);
+            s.ptr = nullptr;
+            s.cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 4096);
+        want = (want + 4095) & ~(size_t)4095;
+        hz_status st = ctx_alloc(c, &s.ptr, want);
+        if (st != HZ_OK) return st;
+        s.cap = want;
+    } else if (s.used && s.last_stream != stream) {
+        HZ_HIP(hipStreamWaitEvent(stream, s.last_use, 0), "hipStreamWaitEvent");
+    }
+    return HZ_OK;
+}
+
+static hz_status scratch_release(Scratch &s, hipStream_t stream)
+{
+    HZ_HIP(hipEventRecord(s.last_use, stream), "hipEventRecord");
+    s.last_stream = stream;
+    s.used = true;
+    return HZ_OK;
+}
+
+static void scratch_free(hz_ctx *c, Scratch &s)
+{
+    if (s.used && s.last_use) (void)hipEventSynchronize(s.last_use);
+    if (s.ptr) ctx_free(c, s.ptr, s.cap);
+    if (s.last_use) (void)hipEventDestroy(s.last_use);
+    s = Scratch{};
+}
+
+extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx **out)
+{
+    if (!out) return fail(HZ_E_INVALID, "hz_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(HZ_E_DEVICE, "hz_ctx_create: no HIP device available (%s)",
+                                              e != hipSuccess ? hipGetErrorString(e) : "0 devices");
+    if (device < 0 || device >= n) return fail(HZ_E_DEVICE, "hz_ctx_create: device %d out of range [0, %d)", device, n);
+    HZ_HIP(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    HZ_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    size_t free_b = 0, total_b = 0;
+    HZ_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    hz_ctx *c = new hz_ctx();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    const uint64_t gib = 1ull << 30;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (free_b > gib ? free_b - gib : free_b / 2);
+    for (int d = 0; d < 3; ++d) c->march_bpc[d] = march_blocks_per_cu(d);
+    c->pinned.resize(8);
+    *out = c;
+    return HZ_OK;
+}
+
+static void field_destroy(hz_field *f)
+{
+    if (f->used && f->last_use) (void)hipEventSynchronize(f->last_use);
+    if (f->data) ctx_free(f->ctx, f->data, f->bytes);
+    if (f->last_use) (void)hipEventDestroy(f->last_use);
+    delete f;
+}
+
+// Return a field's memory to the context pool; its last_use event orders any
+// reuse after the work that read it, so releasing never blocks the host.
+static void field_recycle(hz_field *f)
+{
+    hz_ctx *c = f->ctx;
+    if (!f->used) {
+        field_destroy(f);
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> g(c->pool_mu);
+        c->pool.push_back({f->data, (size_t)f->bytes, f->last_use});
+    }
+    delete f;
+}
+
+// Free pooled blocks (waiting for their last use) until `need` more bytes fit
+// the budget or the pool is empty.
+static void pool_trim(hz_ctx *c, size_t need)
+{
+    std::lock_guard<std::mutex> g(c->pool_mu);
+    while (!c->pool.empty() && c->used.load() + need > c->budget) {
+        hz_ctx::PoolBlock b = c->pool.back();
+        c->pool.pop_back();
+        (void)hipEventSynchronize(b.ready);
+        (void)hipEventDestroy(b.ready);
+        ctx_free(c, b.ptr, b.bytes);
+    }
+}
+
+static void pool_free_all(hz_ctx *c) { pool_trim(c, (size_t)-1 / 2); }
+
+// ---------------------------------------------------------------------------
+// per-kernel event timing
+// ---------------------------------------------------------------------------
+static hipEvent_t prof_begin(hz_ctx *c, hipStream_t s)
+{
+    if (!c->prof_on) return nullptr;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    hipEvent_t e = nullptr;
+    if (!c->prof_free.empty()) {
+        e = c->prof_free.back();
+        c->prof_free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void prof_flush_locked(hz_ctx *c)
+{
+    for (hz_ctx::ProfRec &r : c->prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &acc = c->prof_acc[r.name];
+            acc.first += ms;
+            acc.second += 1;
+        }
+        c->prof_free.push_back(r.a);
+        c->prof_free.push_back(r.b);
+    }
+    c->prof_pending.clear();
+}
+
+static void prof_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a)
+{
+    if (!a) return;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    hipEvent_t b = nullptr;
+    if (!c->prof_free.empty()) {
+        b = c->prof_free.back();
+        c->prof_free.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+        c->prof_free.push_back(a);
+        return;
+    }
+    if (hipEventRecord(b, s) != hipSuccess) {
+        c->prof_free.push_back(a);
+        c->prof_free.push_back(b);
+        return;
+    }
+    c->prof_pending.push_back({name, a, b});
+    if (c->prof_pending.size() > 65536) prof_flush_locked(c);
+}
+
+extern "C" hz_status hz_profile_enable(hz_ctx *c, int32_t enable)
+{
+    if (!c) return fail(HZ_E_INVALID, "hz_profile_enable: ctx is NULL");
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    c->prof_on = enable != 0;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_profile_read(hz_ctx *c, const char *kernel, double *total_ms, int64_t *launches,
+                                     int32_t reset)
+{
+    if (!c || !kernel) return fail(HZ_E_INVALID, "hz_profile_read: NULL argument");
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    prof_flush_locked(c);
+    auto it = c->prof_acc.find(kernel);
+    if (total_ms) *total_ms = it == c->prof_acc.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == c->prof_acc.end() ? 0 : it->second.second;
+    if (reset) c->prof_acc.clear();
+    return HZ_OK;
+}
+
+extern "C" void hz_ctx_destroy(hz_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->server) {
+        server_destroy(c->server);
+        c->server = nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> g(c->fields_mu);
+        for (hz_field *f : c->fields) field_destroy(f);
+        c->fields.clear();
+    }
+    pool_free_all(c);
+    {
+        std::lock_guard<std::mutex> g(c->prof_mu);
+        prof_flush_locked(c);
+        for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
+        c->prof_free.clear();
+    }
+    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->jobs, &c->hits,
+                       &c->counters})
+        scratch_free(c, *s);
+    for (PinnedSlot &p : c->pinned) {
+        if (p.used && p.done) (void)hipEventSynchronize(p.done);
+        if (p.host) (void)hipHostFree(p.host);
+        if (p.done) (void)hipEventDestroy(p.done);
+    }
+    delete c;
+}
+
+extern "C" hz_status hz_ctx_memory(const hz_ctx *c, uint64_t *used_bytes, uint64_t *budget_bytes)
+{
+    if (!c) return fail(HZ_E_INVALID, "hz_ctx_memory: ctx is NULL");
+    if (used_bytes) *used_bytes = c->used.load();
+    if (budget_bytes) *budget_bytes = c->budget;
+    return HZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+static hz_status check_grid(const hz_grid *g, const char *fn)
+{
+    if (!g) return fail(HZ_E_INVALID, "%s: grid is NULL", fn);
+    int64_t nv = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(std::isfinite(g->lo[a]) && std::isfinite(g->hi[a]) && g->hi[a] > g->lo[a]))
+            return fail(HZ_E_INVALID, "%s: grid axis %d needs finite lo < hi", fn, a);
+        if (g->res[a] < 2) return fail(HZ_E_INVALID, "%s: grid res[%d] = %d < 2", fn, a, g->res[a]);
+        nv *= g->res[a];
+        if (nv > INT32_MAX) return fail(HZ_E_INVALID, "%s: more than 2^31 - 1 voxels", fn);
+    }
+    return HZ_OK;
+}
+
+static hz_status check_dtype(hz_dtype dt, float scale, const char *fn)
+{
+    if (dt != HZ_F32 && dt != HZ_F16 && dt != HZ_BF16) return fail(HZ_E_INVALID, "%s: unknown dtype %d", fn, (int)dt);
+    if (!(std::isfinite(scale) && scale > 0.0f)) return fail(HZ_E_INVALID, "%s: store_scale must be > 0", fn);
+    if (dt == HZ_F32 && scale != 1.0f) return fail(HZ_E_INVALID, "%s: store_scale must be 1 for HZ_F32", fn);
+    return HZ_OK;
+}
+
+static uint64_t field_bytes(const hz_grid *g, hz_dtype dt)
+{
+    return (uint64_t)g->res[0] * g->res[1] * g->res[2] * (dt == HZ_F32 ? 16u : 8u);
+}
+
+static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale, hipStream_t s, hz_field **out)
+{
+    hz_field *f = new hz_field();
+    f->ctx = c;
+    f->grid = *g;
+    f->dtype = dt;
+    f->store_scale = scale;
+    f->bytes = field_bytes(g, dt);
+    {
+        // reuse a released block of the same size, ordered after its last use
+        std::lock_guard<std::mutex> lk(c->pool_mu);
+        for (size_t i = 0; i < c->pool.size(); ++i)
+            if (c->pool[i].bytes == f->bytes) {
+                f->data = c->pool[i].ptr;
+                f->last_use = c->pool[i].ready;
+                c->pool.erase(c->pool.begin() + (long)i);
+                break;
+            }
+    }
+    if (f->data) {
+        hipError_t e = hipStreamWaitEvent(s, f->last_use, 0);
+        if (e != hipSuccess) {
+            field_destroy(f);
+            return hip_fail(e, "hipStreamWaitEvent");
+        }
+        *out = f;
+        return HZ_OK;
+    }
+    pool_trim(c, f->bytes);
+    hz_status st = ctx_alloc(c, &f->data, f->bytes);
+    if (st != HZ_OK) {
+        delete f;
+        return st;
+    }
+    hipError_t e = hipEventCreateWithFlags(&f->last_use, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        ctx_free(c, f->data, f->bytes);
+        delete f;
+        return hip_fail(e, "hipEventCreate");
+    }
+    *out = f;
+    return HZ_OK;
+}
+
+static hz_status field_mark_used(hz_field *f, hipStream_t s)
+{
+    std::lock_guard<std::mutex> g(f->mu);
+    HZ_HIP(hipEventRecord(f->last_use, s), "hipEventRecord");
+    f->used = true;
+    return HZ_OK;
+}
+
+static void register_field(hz_ctx *c, hz_field *f)
+{
+    std::lock_guard<std::mutex> g(c->fields_mu);
+    c->fields.push_back(f);
+}
+
+// ---------------------------------------------------------------------------
+// index field
+// ---------------------------------------------------------------------------
+
+static hz_status pack_field(hz_ctx *c, const float *dn, const hz_grid *g, hz_field *f, hipStream_t s)
+{
+    int32_t res[3] = {g->res[0], g->res[1], g->res[2]};
+    float inv_sp[3];
+    for (int a = 0; a < 3; ++a) inv_sp[a] = (float)((double)g->res[a] / (g->hi[a] - g->lo[a]));
+    hipEvent_t t0 = prof_begin(c, s);
+    HZ_HIP(launch_grad_pack((int)f->dtype, dn, res, inv_sp, f->store_scale, f->data, s), "grad/pack launch");
+    prof_end(c, s, "grad_pack", t0);
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, const hz_grid *g,
+                                          const hz_splat_params *prm, void *hip_stream, hz_field **out)
+{
+    const char *fn = "hz_splat_index_field";
+    if (!c || !P || !prm || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
+    hz_status st = check_grid(g, fn);
+    if (st != HZ_OK) return st;
+    if (P->n < 1) return fail(HZ_E_INVALID, "%s: particle count %lld < 1", fn, (long long)P->n);
+    if (P->n > INT32_MAX) return fail(HZ_E_INVALID, "%s: more than 2^31 - 1 particles", fn);
+    if (!P->x || !P->y || !P->z || !P->m) return fail(HZ_E_INVALID, "%s: NULL particle array", fn);
+    if (!(std::isfinite(prm->h) && prm->h > 0.0f)) return fail(HZ_E_INVALID, "%s: h must be > 0", fn);
+    if (!std::isfinite(prm->k_gd)) return fail(HZ_E_INVALID, "%s: k_gd must be finite", fn);
+    st = check_dtype(prm->dtype, prm->store_scale, fn);
+    if (st != HZ_OK) return st;
+
+    // cell list over the grid box grown by the support 2h, cells of edge h
+    CellGrid cg{};
+    const double h = prm->h;
+    const double cell = h;
+    int64_t ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = g->lo[a] - 2.0 * h, hi = g->hi[a] + 2.0 * h;
+        const int64_t nc = (int64_t)std::ceil((hi - lo) / cell) + 1;
+        if (nc > (1 << 20)) return fail(HZ_E_INVALID, "%s: h too small for the grid box (%lld cells on axis %d)", fn,
+                                        (long long)nc, a);
+        cg.clo[a] = (float)lo;
+        cg.nc[a] = (int32_t)nc;
+        ncells *= nc;
+    }
+    if (ncells > (1ll << 28)) return fail(HZ_E_INVALID, "%s: h too small for the grid box (%lld cells)", fn,
+                                         (long long)ncells);
+    cg.cell = (float)cell;
+    cg.inv_cell = (float)(1.0 / cell);
+    cg.ncells = (int32_t)ncells;
+
+    SplatParams sp{};
+    for (int a = 0; a < 3; ++a) {
+        sp.lo[a] = (float)g->lo[a];
+        sp.sp[a] = (float)((g->hi[a] - g->lo[a]) / g->res[a]);
+        sp.res[a] = g->res[a];
+    }
+    sp.nbx = (g->res[0] + 3) / 4;
+    sp.nby = (g->res[1] + 3) / 4;
+    sp.nbz = (g->res[2] + 3) / 4;
+    sp.h = prm->h;
+    sp.inv_h = (float)(1.0 / h);
+    sp.support2 = (float)(4.0 * h * h);
+    sp.scale = (float)((double)prm->k_gd / (M_PI * h * h * h));
+    sp.cg = cg;
+
+    HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int32_t n = (int32_t)P->n;
+    const int64_t nv = (int64_t)g->res[0] * g->res[1] * g->res[2];
+    Scratch *bufs[7] = {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn};
+    const size_t sizes[7] = {4u * (size_t)n, 4u * (size_t)(ncells + 1), 4u * (size_t)(ncells + 1),
+                             4u * (size_t)(ncells + 1), 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv};
+    for (int i = 0; i < 7; ++i) {
+        st = scratch_acquire(c, *bufs[i], sizes[i], s);
+        if (st != HZ_OK) return st;
+    }
+    hz_field *f = nullptr;
+    st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
+    if (st != HZ_OK) return st;
+
+    hipEvent_t t0 = prof_begin(c, s);
+    hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
+                                    (uint32_t *)c->start.ptr, (uint32_t *)c->cursor.ptr, (uint32_t *)c->slots.ptr,
+                                    (float4 *)c->sorted.ptr, s);
+    prof_end(c, s, "cell_list", t0);
+    if (e == hipSuccess) {
+        hipEvent_t t1 = prof_begin(c, s);
+        e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr, s);
+        prof_end(c, s, "splat_gather", t1);
+    }
+    if (e != hipSuccess) {
+        field_destroy(f);
+        return hip_fail(e, "splat launch");
+    }
+    st = pack_field(c, (const float *)c->dn.ptr, g, f, s);
+    if (st != HZ_OK) {
+        field_destroy(f);
+        return st;
+    }
+    for (int i = 0; i < 7; ++i) scratch_release(*bufs[i], s);
+    field_mark_used(f, s);
+    register_field(c, f);
+    *out = f;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_index_field_from_grid(hz_ctx *c, const float *dn, const hz_grid *g, hz_dtype dtype,
+                                              float store_scale, void *hip_stream, hz_field **out)
+{
+    const char *fn = "hz_index_field_from_grid";
+    if (!c || !dn || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
+    hz_status st = check_grid(g, fn);
+    if (st != HZ_OK) return st;
+    st = check_dtype(dtype, store_scale, fn);
+    if (st != HZ_OK) return st;
+    HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hz_field *f = nullptr;
+    st = new_field(c, g, dtype, store_scale, s, &f);
+    if (st != HZ_OK) return st;
+    st = pack_field(c, dn, g, f, s);
+    if (st != HZ_OK) {
+        field_destroy(f);
+        return st;
+    }
+    field_mark_used(f, s);
+    register_field(c, f);
+    *out = f;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_field_read(hz_ctx *c, const hz_field *fc, float *dn, float *gx, float *gy, float *gz,
+                                   void *hip_stream)
+{
+    if (!c || !fc) return fail(HZ_E_INVALID, "hz_field_read: NULL argument");
+    hz_field *f = const_cast<hz_field *>(fc);
+    if (f->ctx != c) return fail(HZ_E_INVALID, "hz_field_read: field belongs to another context");
+    HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t nv = (int64_t)f->grid.res[0] * f->grid.res[1] * f->grid.res[2];
+    HZ_HIP(launch_field_unpack((int)f->dtype, f->data, nv, 1.0f / f->store_scale, dn, gx, gy, gz, s), "unpack launch");
+    return field_mark_used(f, s);
+}
+
+extern "C" hz_status hz_field_info(const hz_field *f, hz_grid *grid, hz_dtype *dtype, float *store_scale,
+                                   uint64_t *bytes)
+{
+    if (!f) return fail(HZ_E_INVALID, "hz_field_info: field is NULL");
+    if (grid) *grid = f->grid;
+    if (dtype) *dtype = f->dtype;
+    if (store_scale) *store_scale = f->store_scale;
+    if (bytes) *bytes = f->bytes;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_field_release(hz_ctx *c, hz_field *f)
+{
+    if (!c || !f) return fail(HZ_E_INVALID, "hz_field_release: NULL argument");
+    {
+        std::lock_guard<std::mutex> g(c->fields_mu);
+        auto it = std::find(c->fields.begin(), c->fields.end(), f);
+        if (it == c->fields.end()) return fail(HZ_E_INVALID, "hz_field_release: unknown field");
+        c->fields.erase(it);
+    }
+    (void)hipSetDevice(c->device);
+    field_recycle(f);
+    return HZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tracing
+// ---------------------------------------------------------------------------
+namespace haze {
+
+hz_status check_step(const hz_step *st, const char *fn)
+{
+    if (!st) return fail(HZ_E_INVALID, "%s: step is NULL", fn);
+    if (st->uniform) {
+        if (!(std::isfinite(st->ds_uniform) && st->ds_uniform > 0.0f))
+            return fail(HZ_E_INVALID, "%s: ds_uniform must be > 0", fn);
+    } else {
+        if (!(std::isfinite(st->ds_min) && st->ds_min > 0.0f))
+            return fail(HZ_E_INVALID, "%s: ds_min must be > 0", fn);
+        if (!(std::isfinite(st->ds_max) && st->ds_max >= st->ds_min))
+            return fail(HZ_E_INVALID, "%s: ds_max must be >= ds_min", fn);
+        if (!(std::isfinite(st->theta_max) && st->theta_max > 0.0f))
+            return fail(HZ_E_INVALID, "%s: theta_max must be > 0", fn);
+        if (!(std::isfinite(st->eps) && st->eps >= 0.0f)) return fail(HZ_E_INVALID, "%s: eps must be >= 0", fn);
+    }
+    if (st->max_steps < 1) return fail(HZ_E_INVALID, "%s: max_steps must be >= 1", fn);
+    if (!(std::isfinite(st->tau_term) && st->tau_term >= 0.0f))
+        return fail(HZ_E_INVALID, "%s: tau_term must be >= 0", fn);
+    return HZ_OK;
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Camera frame of a view, computed on the host in double precision.
+hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
+                   const char *fn, int index)
+{
+    if (v->width < 1 || v->height < 1)
+        return fail(HZ_E_INVALID, "%s: view %d has size %dx%d", fn, index, v->width, v->height);
+    if (!(std::isfinite(v->vfov) && v->vfov > 0.0f && v->vfov < (float)M_PI))
+        return fail(HZ_E_INVALID, "%s: view %d vfov must be in (0, pi)", fn, index);
+    double f[3], up[3], pn[3];
+    for (int a = 0; a < 3; ++a) {
+        f[a] = v->fwd[a];
+        up[a] = v->up[a];
+        pn[a] = v->plane_n[a];
+        if (!std::isfinite(v->eye[a]) || !std::isfinite(f[a]) || !std::isfinite(up[a]) ||
+            !std::isfinite(v->plane_p[a]) || !std::isfinite(pn[a]))
+            return fail(HZ_E_INVALID, "%s: view %d has non-finite values", fn, index);
+    }
+    const double fl = std::sqrt(dot3(f, f));
+    if (!(fl > 0.0)) return fail(HZ_E_INVALID, "%s: view %d fwd is zero", fn, index);
+    if (!(dot3(pn, pn) > 0.0)) return fail(HZ_E_INVALID, "%s: view %d plane_n is zero", fn, index);
+    for (double &x : f) x /= fl;
+    double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rl = std::sqrt(dot3(r, r));
+    if (!(rl > 1e-6 * std::sqrt(dot3(up, up))) || !(rl > 0.0))
+        return fail(HZ_E_INVALID, "%s: view %d fwd is parallel to up", fn, index);
+    for (double &x : r) x /= rl;
+    const double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+    std::memset(J, 0, sizeof *J);
+    for (int a = 0; a < 3; ++a) {
+        J->eye[a] = v->eye[a];
+        J->f[a] = (float)f[a];
+        J->r[a] = (float)r[a];
+        J->u[a] = (float)u[a];
+        J->plane_p[a] = v->plane_p[a];
+        J->plane_n[a] = v->plane_n[a];
+    }
+    J->fpx = (float)(0.5 * (double)v->height / std::tan(0.5 * (double)v->vfov));
+    J->half_w = 0.5f * (float)v->width;
+    J->half_h = 0.5f * (float)v->height;
+    J->width = v->width;
+    J->height = v->height;
+    J->tiles_x = (v->width + 7) / 8;
+    J->field = field;
+    J->slot_begin = slot_begin;
+    J->ray_begin = ray_begin;
+    return HZ_OK;
+}
+
+void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G)
+{
+    for (int a = 0; a < 3; ++a) {
+        const double sp = (g.hi[a] - g.lo[a]) / g.res[a];
+        G->lo[a] = (float)g.lo[a];
+        G->hi[a] = (float)g.hi[a];
+        G->inv_sp[a] = (float)(1.0 / sp);
+        G->off[a] = (float)(-g.lo[a] / sp - 0.5);
+        G->maxi[a] = (float)(g.res[a] - 2);
+        G->res[a] = g.res[a];
+    }
+    G->inv_scale = 1.0f / store_scale;
+}
+
+void make_trace_step(const hz_step &st, TraceStep *S)
+{
+    S->uniform = st.uniform ? 1 : 0;
+    S->theta_max = st.theta_max;
+    S->ds_min = st.ds_min;
+    S->ds_max = st.ds_max;
+    S->eps = st.eps;
+    S->ds_uniform = st.ds_uniform;
+    S->tau = st.tau_term;
+    S->max_steps = st.max_steps;
+    const float cap = std::max(st.uniform ? st.ds_uniform : st.ds_max, st.tau_term);
+    S->near_cap = cap * 1.001f + 1e-30f;
+}
+
+}  // namespace haze
+
+// Copy `bytes` from host to device through a pinned staging slot.
+static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    PinnedSlot &p = c->pinned[c->pinned_next];
+    c->pinned_next = (c->pinned_next + 1) % c->pinned.size();
+    if (!p.done) HZ_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming), "hipEventCreate");
+    if (p.used) HZ_HIP(hipEventSynchronize(p.done), "hipEventSynchronize");
+    if (p.cap < bytes) {
+        if (p.host) (void)hipHostFree(p.host);
+        p.host = nullptr;
+        p.cap = 0;
+        HZ_HIP(hipHostMalloc(&p.host, bytes, hipHostMallocDefault), "hipHostMalloc");
+        p.cap = bytes;
+    }
+    std::memcpy(p.host, src, bytes);
+    HZ_HIP(hipMemcpyAsync(dst, p.host, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    HZ_HIP(hipEventRecord(p.done, s), "hipEventRecord");
+    p.used = true;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                                    const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                                    const hz_trace_out *out, void *hip_stream)
+{
+    const char *fn = "hz_trace_views";
+    if (!c || !fc || !views || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
+    hz_field *f = const_cast<hz_field *>(fc);
+    if (f->ctx != c) return fail(HZ_E_INVALID, "%s: field belongs to another context", fn);
+    if (nviews < 1 || nviews > 4096) return fail(HZ_E_INVALID, "%s: nviews = %d outside [1, 4096]", fn, nviews);
+    hz_status st = check_step(step, fn);
+    if (st != HZ_OK) return st;
+    std::vector<TraceJob> jobs((size_t)nviews);
+    int64_t slot = 0, ray = 0;
+    for (int i = 0; i < nviews; ++i) {
+        st = make_job(&views[i], f->data, slot, ray, &jobs[(size_t)i], fn, i);
+        if (st != HZ_OK) return st;
+        const int64_t tiles = (int64_t)((views[i].width + 7) / 8) * ((views[i].height + 7) / 8);
+        slot += tiles * 64;
+        ray += (int64_t)views[i].width * views[i].height;
+    }
+    if (slot > INT32_MAX || ray > INT32_MAX) return fail(HZ_E_INVALID, "%s: more than 2^31 - 1 rays", fn);
+    const bool subset = ray_ids != nullptr;
+    if (!subset && nrays != ray) return fail(HZ_E_INVALID, "%s: nrays = %lld but the views hold %lld rays", fn,
+                                             (long long)nrays, (long long)ray);
+    if (subset && (nrays < 0 || nrays > INT32_MAX)) return fail(HZ_E_INVALID, "%s: bad nrays %lld", fn,
+                                                               (long long)nrays);
+
+    TraceLaunch L{};
+    L.njobs = nviews;
+    L.subset = subset ? 1 : 0;
+    L.nslots = subset ? nrays : slot;
+    L.ray_ids = ray_ids;
+    L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status};
+    if (!subset)
+        for (TraceJob &J : jobs) {
+            const int64_t base = J.ray_begin;
+            J.disp = out->disp ? out->disp + 2 * base : nullptr;
+            J.exit_pos = out->exit_pos ? out->exit_pos + 3 * base : nullptr;
+            J.exit_dir = out->exit_dir ? out->exit_dir + 3 * base : nullptr;
+            J.steps = out->steps ? out->steps + base : nullptr;
+            J.status = out->status ? out->status + base : nullptr;
+        }
+    make_trace_grid(f->grid, f->store_scale, &L.grid);
+    make_trace_step(*step, &L.step);
+    L.refill_min = 16;
+    if (L.nslots == 0) return HZ_OK;
+
+    HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t job_bytes = sizeof(TraceJob) * jobs.size();
+    st = scratch_acquire(c, c->jobs, job_bytes, s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->counters, 256, s);
+    if (st != HZ_OK) return st;
+    st = staged_copy(c, c->jobs.ptr, jobs.data(), job_bytes, s);
+    if (st != HZ_OK) return st;
+    L.jobs = (const TraceJob *)c->jobs.ptr;
+    L.hits = (uint32_t *)c->hits.ptr;
+    L.counters = (uint32_t *)c->counters.ptr;
+    const int dt = (int)f->dtype;
+    const int64_t want_blocks = (L.nslots + 255) / 256;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want_blocks, (int64_t)c->march_bpc[dt] * c->num_cus));
+    hipEvent_t t0 = prof_begin(c, s);
+    HZ_HIP(launch_raygen(L, s), "raygen launch");
+    prof_end(c, s, "raygen", t0);
+    hipEvent_t t1 = prof_begin(c, s);
+    HZ_HIP(launch_march(dt, L, blocks, s), "march launch");
+    prof_end(c, s, "march", t1);
+    scratch_release(c->jobs, s);
+    scratch_release(c->hits, s);
+    scratch_release(c->counters, s);
+    return field_mark_used(f, s);
+}
+
+// ---------------------------------------------------------------------------
+// serving entry points (serve.hip holds the scheduler)
+// ---------------------------------------------------------------------------
+namespace haze {
+Server *&ctx_server(hz_ctx *c) { return c->server; }
+const hz_grid &field_grid(const hz_field *f) { return f->grid; }
+hz_dtype field_dtype(const hz_field *f) { return f->dtype; }
+float field_scale(const hz_field *f) { return f->store_scale; }
+const void *field_data(const hz_field *f) { return f->data; }
+hz_ctx *field_ctx(const hz_field *f) { return f->ctx; }
+hz_status field_use(hz_field *f, hipStream_t s) { return field_mark_used(f, s); }
+int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
+hipEvent_t profile_begin(hz_ctx *c, hipStream_t s) { return prof_begin(c, s); }
+void profile_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a) { prof_end(c, s, name, a); }
+hz_status set_error(hz_status s, const char *msg) { return fail(s, "%s", msg); }
+}  // namespace haze

@@ -1,0 +1,28 @@
+// serve.h -- serving loop of libhaze.so (internal).
+#pragma once
+
+#include "haze.h"
+
+#include <hip/hip_runtime.h>
+
+namespace haze {
+struct Server;
+void server_destroy(Server *s);
+
+// context/field accessors implemented in runtime.hip
+hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes);
+void ctx_free(hz_ctx *c, void *p, size_t bytes);
+int ctx_device(const hz_ctx *c);
+int ctx_num_cus(const hz_ctx *c);
+Server *&ctx_server(hz_ctx *c);
+const hz_grid &field_grid(const hz_field *f);
+hz_dtype field_dtype(const hz_field *f);
+float field_scale(const hz_field *f);
+const void *field_data(const hz_field *f);
+hz_ctx *field_ctx(const hz_field *f);
+hz_status field_use(hz_field *f, hipStream_t s);
+int march_blocks(hz_ctx *c, int dt);
+hipEvent_t profile_begin(hz_ctx *c, hipStream_t s);
+void profile_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a);
+hz_status set_error(hz_status s, const char *msg);
+}  // namespace haze

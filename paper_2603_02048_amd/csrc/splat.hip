@@ -1,0 +1,348 @@
+// splat.hip -- particles -> refractive-index field on gfx950.
+//
+// Paper Sec. 3.3.1: density is rasterised to a regular grid by SPH kernel
+// splatting at voxel centres, mapped to n = 1 + K_GD rho (Eq. 12), and its
+// gradient grad n = K_GD grad rho is taken by finite differences on the grid
+// (Eq. 13).  The field stores delta_n = n - 1 and grad n per voxel.
+//
+// Pipeline (all integer work exact, so the result is bitwise repeatable):
+//   k_cell_count   particle -> cell id (cells of edge h over the grid box grown
+//                  by 2h), integer histogram with atomics
+//   k_scan_cells   exclusive prefix sum of the histogram (one workgroup)
+//   k_cell_scatter particle index -> a slot of its cell (arbitrary order)
+//   k_cell_order   per cell, rank the slots by particle index (stable order)
+//                  and gather (x, y, z, m) into cell-sorted float4 records
+//   k_splat        one wave per 4x4x4 voxel brick: every lane owns a voxel and
+//                  all lanes walk the same candidate particles (wave-uniform
+//                  scalar loads) row by row of the cell list, culled by the
+//                  brick-to-row distance, summing m_j W in a fixed order
+//   k_grad_pack    central differences (one-sided on faces) and packing of
+//                  (delta_n, grad) into F32 / F16 / BF16 voxels
+#include "haze_device.h"
+
+#include <hip/hip_fp16.h>
+
+namespace haze {
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, int nc)
+{
+    float c = floorf((x - clo) * inv_cell);
+    if (!(c >= 0.0f) || c >= (float)nc) return -1;
+    return (int)c;
+}
+
+// Particle -> cell id (0xffffffff when outside the grown box) + histogram.
+__global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x, const float *__restrict__ y,
+                                                    const float *__restrict__ z, int32_t n, CellGrid cg,
+                                                    uint32_t *__restrict__ cid, uint32_t *__restrict__ count)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cx = cell_coord(x[i], cg.clo[0], cg.inv_cell, cg.nc[0]);
+    int cy = cell_coord(y[i], cg.clo[1], cg.inv_cell, cg.nc[1]);
+    int cz = cell_coord(z[i], cg.clo[2], cg.inv_cell, cg.nc[2]);
+    uint32_t id = 0xffffffffu;
+    if (cx >= 0 && cy >= 0 && cz >= 0) {
+        id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
+        atomicAdd(&count[id], 1u);
+    }
+    cid[i] = id;
+}
+
+// Exclusive scan of count[0..n) into start[0..n]; start[n] = total.  One
+// workgroup of 1024 threads; thread t owns a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_scan_cells(const uint32_t *__restrict__ count, uint32_t *__restrict__ start,
+                                                     int32_t n)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk;
+    const int e = min(n, b + chunk);
+    uint32_t s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the 1024 chunk sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int i = b; i < e; ++i) {
+        start[i] = run;
+        run += count[i];
+    }
+    if (t == 1023) start[n] = part[1023];
+}
+
+// Every binned particle takes a slot of its cell.
+__global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict__ cid, int32_t n,
+                                                      uint32_t *__restrict__ cursor, uint32_t *__restrict__ slots)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = cid[i];
+    if (c == 0xffffffffu) return;
+    uint32_t pos = atomicAdd(&cursor[c], 1u);
+    slots[pos] = (uint32_t)i;
+}
+
+// One wave per cell: the rank of a particle inside its cell is the number of
+// cell members with a smaller index, which puts each cell in index order
+// whatever order k_cell_scatter produced.
+__global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__ start,
+                                                    const uint32_t *__restrict__ slots, int32_t ncells,
+                                                    const float *__restrict__ x, const float *__restrict__ y,
+                                                    const float *__restrict__ z, const float *__restrict__ m,
+                                                    float4 *__restrict__ sorted)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= ncells) return;
+    const uint32_t b = start[c], e = start[c + 1];
+    for (uint32_t s = b + lane; s < e; s += 64) {
+        const uint32_t me = slots[s];
+        uint32_t rank = 0;
+        for (uint32_t t = b; t < e; ++t) rank += slots[t] < me ? 1u : 0u;
+        sorted[b + rank] = make_float4(x[me], y[me], z[me], m[me]);
+    }
+}
+
+// One wave per 4x4x4 brick, lane = voxel (lane & 3, (lane >> 2) & 3, lane >> 4).
+// Workgroups are remapped so that each XCD (workgroups are dealt round-robin
+// over the 8 XCDs) walks a contiguous run of bricks and keeps its particle
+// rows in its own L2.
+__global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
+                                               const float4 *__restrict__ parts, int32_t nbricks, int32_t per_xcd,
+                                               float *__restrict__ dn)
+{
+    const int32_t logical = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t brick = logical * 4 + wave;
+    if (brick >= nbricks) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t bx = brick % P.nbx;
+    const int32_t by = (brick / P.nbx) % P.nby;
+    const int32_t bz = brick / (P.nbx * P.nby);
+    const int32_t vx = bx * 4 + (lane & 3), vy = by * 4 + ((lane >> 2) & 3), vz = bz * 4 + (lane >> 4);
+    const bool valid = vx < P.res[0] && vy < P.res[1] && vz < P.res[2];
+    const float cx = P.lo[0] + ((float)vx + 0.5f) * P.sp[0];
+    const float cy = P.lo[1] + ((float)vy + 0.5f) * P.sp[1];
+    const float cz = P.lo[2] + ((float)vz + 0.5f) * P.sp[2];
+
+    // brick AABB of voxel centres (wave-uniform)
+    float blo[3], bhi[3];
+    {
+        const int32_t b0[3] = {bx * 4, by * 4, bz * 4};
+        for (int a = 0; a < 3; ++a) {
+            const int32_t i1 = min(b0[a] + 3, P.res[a] - 1);
+            blo[a] = P.lo[a] + ((float)b0[a] + 0.5f) * P.sp[a];
+            bhi[a] = P.lo[a] + ((float)i1 + 0.5f) * P.sp[a];
+        }
+    }
+    const CellGrid &cg = P.cg;
+    const float R = 2.0f * P.h;
+    // conservative cell ranges (one cell of slack absorbs rounding)
+    const int cz0 = max(0, (int)floorf((blo[2] - R - cg.clo[2]) * cg.inv_cell) - 1);
+    const int cz1 = min(cg.nc[2] - 1, (int)floorf((bhi[2] + R - cg.clo[2]) * cg.inv_cell) + 1);
+    const int cy0 = max(0, (int)floorf((blo[1] - R - cg.clo[1]) * cg.inv_cell) - 1);
+    const int cy1 = min(cg.nc[1] - 1, (int)floorf((bhi[1] + R - cg.clo[1]) * cg.inv_cell) + 1);
+
+    float acc = 0.0f;
+    for (int kz = cz0; kz <= cz1; ++kz) {
+        const float zl = cg.clo[2] + (float)kz * cg.cell;
+        const float gz = fmaxf(0.0f, fmaxf(zl - bhi[2], blo[2] - (zl + cg.cell)));
+        for (int ky = cy0; ky <= cy1; ++ky) {
+            const float yl = cg.clo[1] + (float)ky * cg.cell;
+            const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
+            // 1.0001 R^2 keeps the cull conservative under rounding
+            const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
+            if (rem <= 0.0f) continue;
+            const float dxm = sqrtf(rem);
+            const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
+            const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
+            if (kx0 > kx1) continue;
+            const int row = (kz * cg.nc[1] + ky) * cg.nc[0];
+            const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
+            const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
+            for (uint32_t s = s0; s < s1; ++s) {
+                const float4 q = parts[s];
+                const float dx = cx - q.x, dy = cy - q.y, dz = cz - q.z;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                if (r2 < P.support2) {
+                    const float qq = __builtin_amdgcn_sqrtf(r2) * P.inv_h;
+                    const float a = fmaxf(2.0f - qq, 0.0f);
+                    const float b = fmaxf(1.0f - qq, 0.0f);
+                    // M4 spline: 1 - 1.5q^2 + 0.75q^3 (q<1), 0.25(2-q)^3 (1<=q<2)
+                    const float w = 0.25f * (a * a * a) - b * b * b;
+                    acc = fmaf(q.w, w, acc);
+                }
+            }
+        }
+    }
+    if (valid) dn[((int64_t)vz * P.res[1] + vy) * P.res[0] + vx] = acc * P.scale;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t rx, int32_t ry, int32_t rz,
+                                                   float ix, float iy, float iz, float scale, void *__restrict__ out)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nv = (int64_t)rx * ry * rz;
+    if (v >= nv) return;
+    const int32_t i = (int32_t)(v % rx);
+    const int32_t j = (int32_t)((v / rx) % ry);
+    const int32_t k = (int32_t)(v / ((int64_t)rx * ry));
+    const int64_t sy = rx, sz = (int64_t)rx * ry;
+    const float c = dn[v];
+    float g[3];
+    {
+        // inside: (f[i+1] - f[i-1]) / (2 d); faces: one-sided first difference
+        const int32_t idx[3] = {i, j, k};
+        const int32_t R[3] = {rx, ry, rz};
+        const int64_t st[3] = {1, sy, sz};
+        const float inv[3] = {ix, iy, iz};
+        for (int a = 0; a < 3; ++a) {
+            if (idx[a] == 0)
+                g[a] = (dn[v + st[a]] - c) * inv[a];
+            else if (idx[a] == R[a] - 1)
+                g[a] = (c - dn[v - st[a]]) * inv[a];
+            else
+                g[a] = (dn[v + st[a]] - dn[v - st[a]]) * (0.5f * inv[a]);
+        }
+    }
+    if (DT == DT_F32) {
+        reinterpret_cast<float4 *>(out)[v] = make_float4(c, g[0], g[1], g[2]);
+    } else if (DT == DT_F16) {
+        ushort4 h;
+        h.x = __half_as_ushort(__float2half_rn(c * scale));
+        h.y = __half_as_ushort(__float2half_rn(g[0] * scale));
+        h.z = __half_as_ushort(__float2half_rn(g[1] * scale));
+        h.w = __half_as_ushort(__float2half_rn(g[2] * scale));
+        reinterpret_cast<ushort4 *>(out)[v] = h;
+    } else {
+        ushort4 h;
+        h.x = f32_to_bf16_rne(c * scale);
+        h.y = f32_to_bf16_rne(g[0] * scale);
+        h.z = f32_to_bf16_rne(g[1] * scale);
+        h.w = f32_to_bf16_rne(g[2] * scale);
+        reinterpret_cast<ushort4 *>(out)[v] = h;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_field_unpack(const void *__restrict__ in, int64_t nv, float inv_scale,
+                                                      float *__restrict__ dn, float *__restrict__ gx,
+                                                      float *__restrict__ gy, float *__restrict__ gz)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    float4 f;
+    if (DT == DT_F32) {
+        f = reinterpret_cast<const float4 *>(in)[v];
+    } else {
+        const ushort4 h = reinterpret_cast<const ushort4 *>(in)[v];
+        if (DT == DT_F16) {
+            f = make_float4(__half2float(__ushort_as_half(h.x)), __half2float(__ushort_as_half(h.y)),
+                            __half2float(__ushort_as_half(h.z)), __half2float(__ushort_as_half(h.w)));
+        } else {
+            f = make_float4(__uint_as_float((uint32_t)h.x << 16), __uint_as_float((uint32_t)h.y << 16),
+                            __uint_as_float((uint32_t)h.z << 16), __uint_as_float((uint32_t)h.w << 16));
+        }
+        f.x *= inv_scale;
+        f.y *= inv_scale;
+        f.z *= inv_scale;
+        f.w *= inv_scale;
+    }
+    if (dn) dn[v] = f.x;
+    if (gx) gx[v] = f.y;
+    if (gy) gy[v] = f.z;
+    if (gz) gz[v] = f.w;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers (sizes validated by the caller)
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
+                            const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *cursor,
+                            uint32_t *slots, float4 *sorted, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 1, 256)), dim3(256), 0, s, count, 0u,
+                       (int64_t)cg.ncells + 1);
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, n, cg, cid, count);
+    hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, s, count, start, cg.ncells);
+    hipError_t e = hipMemcpyAsync(cursor, start, sizeof(uint32_t) * (size_t)cg.ncells, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, n, cursor, slots);
+    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(cg.ncells, 4)), dim3(256), 0, s, start, slots, cg.ncells, x, y,
+                       z, m, sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn, hipStream_t s)
+{
+    const int32_t nbricks = P.nbx * P.nby * P.nbz;
+    const int32_t nblocks = (nbricks + 3) / 4;
+    const int32_t per_xcd = (nblocks + 7) / 8;
+    hipLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, P, start, sorted, nbricks, per_xcd,
+                       dn);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_pack(int dtype, const float *dn, const int32_t res[3], const float inv_sp[3], float scale,
+                            void *out, hipStream_t s)
+{
+    const int64_t nv = (int64_t)res[0] * res[1] * res[2];
+    const dim3 g(blocks_for(nv, 256)), b(256);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
+                           inv_sp[2], scale, out);
+    else if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
+                           inv_sp[2], scale, out);
+    else
+        hipLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
+                           inv_sp[2], scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_unpack(int dtype, const void *in, int64_t nv, float inv_scale, float *dn, float *gx,
+                               float *gy, float *gz, hipStream_t s)
+{
+    const dim3 g(blocks_for(nv, 256)), b(256);
+    if (dtype == DT_F32)
+        hipLaunchKernelGGL(k_field_unpack<DT_F32>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+    else if (dtype == DT_F16)
+        hipLaunchKernelGGL(k_field_unpack<DT_F16>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+    else
+        hipLaunchKernelGGL(k_field_unpack<DT_BF16>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace haze

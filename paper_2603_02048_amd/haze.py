@@ -1,0 +1,351 @@
+"""Thin Python binding of libhaze.so (include/haze.h).
+
+Argument marshalling only: every step of the splat-and-trace path runs in the
+library's gfx950 kernels.  PyTorch provides device memory (tensors) and the
+current HIP stream.  Loading fails loudly when the library has not been built
+(`python -m paper_2603_02048_amd.build`); there is no CPU fallback.
+
+Function names follow the C ABI without the `hz_` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhaze.so")
+
+OK, PENDING = 0, 1
+E_INVALID, E_NOMEM, E_BUDGET, E_DEVICE, E_NOTFOUND, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+F32, F16, BF16 = 0, 1, 2
+DTYPES = {"f32": F32, "f16": F16, "bf16": BF16}
+RAY_OK, RAY_MAXSTEPS, RAY_NOHIT, RAY_NONFINITE, RAY_BAD_ID = 0, 1, 2, 3, 4
+
+
+class HazeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class hz_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("m", C.c_void_p)]
+
+
+class hz_grid(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3), ("res", C.c_int32 * 3)]
+
+
+class hz_splat_params(C.Structure):
+    _fields_ = [("k_gd", C.c_float), ("h", C.c_float), ("dtype", C.c_int), ("store_scale", C.c_float)]
+
+
+class hz_view(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("fwd", C.c_float * 3), ("up", C.c_float * 3), ("vfov", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32), ("plane_p", C.c_float * 3), ("plane_n", C.c_float * 3)]
+
+
+class hz_step(C.Structure):
+    _fields_ = [("uniform", C.c_int32), ("theta_max", C.c_float), ("ds_min", C.c_float), ("ds_max", C.c_float),
+                ("eps", C.c_float), ("ds_uniform", C.c_float), ("max_steps", C.c_int32), ("tau_term", C.c_float)]
+
+
+class hz_trace_out(C.Structure):
+    _fields_ = [("disp", C.c_void_p), ("exit_pos", C.c_void_p), ("exit_dir", C.c_void_p), ("steps", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_profile_enable",
+           "hz_profile_read", "hz_splat_index_field",
+           "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
+           "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
+           "hz_server_stop"]
+
+_lib = None
+
+
+def lib():
+    """Load libhaze.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhaze.so not built ({LIB_PATH}); run `python -m paper_2603_02048_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, S = C.c_void_p, C.c_int
+        L.hz_ctx_create.argtypes, L.hz_ctx_create.restype = [C.c_int, C.c_uint64, C.POINTER(C.c_void_p)], S
+        L.hz_ctx_destroy.argtypes, L.hz_ctx_destroy.restype = [P], None
+        L.hz_last_error.argtypes, L.hz_last_error.restype = [], C.c_char_p
+        L.hz_ctx_memory.argtypes, L.hz_ctx_memory.restype = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], S
+        L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
+        L.hz_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+        L.hz_profile_read.restype = S
+        L.hz_splat_index_field.argtypes = [P, C.POINTER(hz_particles), C.POINTER(hz_grid),
+                                           C.POINTER(hz_splat_params), P, C.POINTER(C.c_void_p)]
+        L.hz_splat_index_field.restype = S
+        L.hz_index_field_from_grid.argtypes = [P, P, C.POINTER(hz_grid), C.c_int, C.c_float, P,
+                                               C.POINTER(C.c_void_p)]
+        L.hz_index_field_from_grid.restype = S
+        L.hz_field_read.argtypes, L.hz_field_read.restype = [P, P, P, P, P, P, P], S
+        L.hz_field_info.argtypes = [P, C.POINTER(hz_grid), C.POINTER(C.c_int), C.POINTER(C.c_float),
+                                    C.POINTER(C.c_uint64)]
+        L.hz_field_info.restype = S
+        L.hz_field_release.argtypes, L.hz_field_release.restype = [P, P], S
+        L.hz_trace_views.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), P, C.c_int64,
+                                     C.POINTER(hz_trace_out), P]
+        L.hz_trace_views.restype = S
+        L.hz_server_start.argtypes, L.hz_server_start.restype = [P, C.c_int32, C.c_int64], S
+        L.hz_submit.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), C.POINTER(C.c_uint64)]
+        L.hz_submit.restype = S
+        L.hz_poll.argtypes, L.hz_poll.restype = [P, C.c_uint64, C.POINTER(C.c_double)], S
+        L.hz_request_outputs.argtypes = [P, C.c_uint64, C.POINTER(hz_trace_out), C.POINTER(C.c_int64)]
+        L.hz_request_outputs.restype = S
+        L.hz_request_release.argtypes, L.hz_request_release.restype = [P, C.c_uint64], S
+        L.hz_server_stop.argtypes, L.hz_server_stop.restype = [P], S
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().hz_last_error().decode()
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise HazeError(status, f"{what}: {last_error()}")
+    return status
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_grid(grid) -> hz_grid:
+    g = hz_grid()
+    for a in range(3):
+        g.lo[a] = float(grid.lo[a])
+        g.hi[a] = float(grid.hi[a])
+        g.res[a] = int(grid.res[a])
+    return g
+
+
+def make_view(v) -> hz_view:
+    o = hz_view()
+    for a in range(3):
+        o.eye[a] = float(v.eye[a])
+        o.fwd[a] = float(v.fwd[a])
+        o.up[a] = float(v.up[a])
+        o.plane_p[a] = float(v.plane_p[a])
+        o.plane_n[a] = float(v.plane_n[a])
+    o.vfov = float(v.vfov)
+    o.width = int(v.width)
+    o.height = int(v.height)
+    return o
+
+
+def make_views(views: Sequence) -> C.Array:
+    arr = (hz_view * len(views))()
+    for i, v in enumerate(views):
+        arr[i] = make_view(v)
+    return arr
+
+
+def make_step(st) -> hz_step:
+    return hz_step(int(st.uniform), float(st.theta_max), float(st.ds_min), float(st.ds_max), float(st.eps),
+                   float(st.ds_uniform), int(min(st.max_steps, 2 ** 31 - 1)), float(st.tau_term))
+
+
+@dataclass
+class DeviceParticles:
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    m: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.x.numel())
+
+
+def upload_particles(p: W.Particles, device="cuda") -> DeviceParticles:
+    t = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device) for a in (p.x, p.y, p.z, p.m)]
+    return DeviceParticles(*t)
+
+
+class Field:
+    """A device-resident (delta_n, grad n) field owned by a Context."""
+
+    def __init__(self, ctx: "Context", handle: int, grid):
+        self.ctx = ctx
+        self.handle = handle
+        self.grid = grid
+
+    def info(self) -> dict:
+        g = hz_grid()
+        dt = C.c_int()
+        sc = C.c_float()
+        nb = C.c_uint64()
+        _check(lib().hz_field_info(C.c_void_p(self.handle), C.byref(g), C.byref(dt), C.byref(sc), C.byref(nb)),
+               "field_info")
+        return dict(res=tuple(g.res), lo=tuple(g.lo), hi=tuple(g.hi), dtype=dt.value, store_scale=sc.value,
+                    bytes=nb.value)
+
+    def release(self):
+        if self.handle:
+            _check(lib().hz_field_release(C.c_void_p(self.ctx.handle), C.c_void_p(self.handle)), "field_release")
+            self.handle = 0
+
+
+class Context:
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().hz_ctx_create(int(device), int(budget_bytes), C.byref(h)), "ctx_create")
+        self.handle = h.value
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().hz_ctx_destroy(C.c_void_p(self.handle))
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def memory(self) -> tuple:
+        u, b = C.c_uint64(), C.c_uint64()
+        _check(lib().hz_ctx_memory(C.c_void_p(self.handle), C.byref(u), C.byref(b)), "ctx_memory")
+        return u.value, b.value
+
+    def profile_enable(self, enable: bool = True):
+        _check(lib().hz_profile_enable(C.c_void_p(self.handle), 1 if enable else 0), "profile_enable")
+
+    def profile_read(self, kernel: str, reset: bool = False) -> tuple:
+        """(total milliseconds, launch count) of a kernel since the last reset."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().hz_profile_read(C.c_void_p(self.handle), kernel.encode(), C.byref(ms), C.byref(n),
+                                     1 if reset else 0), "profile_read")
+        return ms.value, n.value
+
+    # -- index field ------------------------------------------------------
+    def splat_index_field(self, particles: DeviceParticles, grid, k_gd: float, h: float, dtype: str = "f32",
+                          store_scale: float = 1.0, stream=None) -> Field:
+        P = hz_particles(particles.n, _ptr(particles.x), _ptr(particles.y), _ptr(particles.z), _ptr(particles.m))
+        prm = hz_splat_params(float(k_gd), float(h), DTYPES[dtype], float(store_scale))
+        out = C.c_void_p()
+        g = make_grid(grid)
+        _check(lib().hz_splat_index_field(C.c_void_p(self.handle), C.byref(P), C.byref(g), C.byref(prm),
+                                          _stream(stream), C.byref(out)), "splat_index_field")
+        return Field(self, out.value, grid)
+
+    def index_field_from_grid(self, dn: torch.Tensor, grid, dtype: str = "f32", store_scale: float = 1.0,
+                              stream=None) -> Field:
+        assert dn.dtype == torch.float32 and dn.is_contiguous() and dn.is_cuda
+        out = C.c_void_p()
+        g = make_grid(grid)
+        _check(lib().hz_index_field_from_grid(C.c_void_p(self.handle), _ptr(dn), C.byref(g), DTYPES[dtype],
+                                              float(store_scale), _stream(stream), C.byref(out)),
+               "index_field_from_grid")
+        return Field(self, out.value, grid)
+
+    def field_read(self, field: Field, stream=None) -> tuple:
+        res = [int(r) for r in field.grid.res]
+        shape = (res[2], res[1], res[0])
+        arrs = [torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(4)]
+        _check(lib().hz_field_read(C.c_void_p(self.handle), C.c_void_p(field.handle), *[_ptr(a) for a in arrs],
+                                   _stream(stream)), "field_read")
+        return tuple(arrs)
+
+    # -- tracing ----------------------------------------------------------
+    def trace_views(self, field: Field, views: Sequence, step, ray_ids: Optional[torch.Tensor] = None,
+                    out: Optional[dict] = None, stream=None) -> dict:
+        total = sum(int(v.width) * int(v.height) for v in views)
+        n = total if ray_ids is None else int(ray_ids.numel())
+        if out is None:
+            out = alloc_outputs(n)
+        o = hz_trace_out(_ptr(out.get("disp")), _ptr(out.get("exit_pos")), _ptr(out.get("exit_dir")),
+                         _ptr(out.get("steps")), _ptr(out.get("status")))
+        vs = make_views(views)
+        st = make_step(step)
+        if ray_ids is not None:
+            assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
+        _check(lib().hz_trace_views(C.c_void_p(self.handle), C.c_void_p(field.handle), vs, len(views),
+                                    C.byref(st), _ptr(ray_ids), n, C.byref(o), _stream(stream)), "trace_views")
+        return out
+
+    # -- serving ----------------------------------------------------------
+    def server_start(self, slots: int = 4, max_batch_rays: int = 1 << 23):
+        _check(lib().hz_server_start(C.c_void_p(self.handle), int(slots), int(max_batch_rays)), "server_start")
+
+    def submit(self, field: Field, views: Sequence, step) -> int:
+        t = C.c_uint64()
+        _check(lib().hz_submit(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views), len(views),
+                               C.byref(make_step(step)), C.byref(t)), "submit")
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[float]:
+        lat = C.c_double()
+        s = _check(lib().hz_poll(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(lat)), "poll")
+        return None if s == PENDING else lat.value
+
+    def request_outputs(self, ticket: int) -> dict:
+        """Copies of a completed request's outputs (torch tensors on the GPU)."""
+        o = hz_trace_out()
+        n = C.c_int64()
+        _check(lib().hz_request_outputs(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(o), C.byref(n)),
+               "request_outputs")
+        return _wrap_device_outputs(o, n.value)
+
+    def request_release(self, ticket: int):
+        _check(lib().hz_request_release(C.c_void_p(self.handle), C.c_uint64(ticket)), "request_release")
+
+    def server_stop(self):
+        _check(lib().hz_server_stop(C.c_void_p(self.handle)), "server_stop")
+
+
+def alloc_outputs(n: int, device="cuda") -> dict:
+    return dict(disp=torch.empty((n, 2), dtype=torch.float32, device=device),
+                exit_pos=torch.empty((n, 3), dtype=torch.float32, device=device),
+                exit_dir=torch.empty((n, 3), dtype=torch.float32, device=device),
+                steps=torch.empty(n, dtype=torch.int32, device=device),
+                status=torch.empty(n, dtype=torch.uint8, device=device))
+
+
+def _wrap_device_outputs(o: hz_trace_out, n: int) -> dict:
+    """Copy library-owned device arrays into fresh torch tensors (device to device)."""
+    out = alloc_outputs(n)
+    spec = [("disp", o.disp, 8), ("exit_pos", o.exit_pos, 12), ("exit_dir", o.exit_dir, 12), ("steps", o.steps, 4),
+            ("status", o.status, 1)]
+    hip = _hip_runtime()
+    for name, src, per in spec:
+        if src and n:
+            rc = hip.hipMemcpy(C.c_void_p(out[name].data_ptr()), C.c_void_p(src), C.c_size_t(per * n), 3)
+            if rc != 0:
+                raise HazeError(E_DEVICE, f"hipMemcpy of request outputs failed ({rc})")
+    return out
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip
