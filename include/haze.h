@@ -96,6 +96,15 @@ const char *hz_last_error(void);
  * its budget. */
 hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 
+/* Tuning knobs of the tracer's persistent march (results do not depend on
+ * them, only speed):
+ *   "march.refill_min"     refill a wave once this many of its 64 lanes are
+ *                          idle, 1..64 (default 16)
+ *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
+ *                          0 = as many as fit (default 0)
+ * Errors: HZ_E_INVALID (unknown key or value out of range). */
+hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
+
 /* Per-kernel timing with HIP events recorded around every launch the context
  * makes on the caller's stream (kernels: "cell_list", "splat_gather",
  * "grad_pack", "raygen", "march").  hz_profile_read waits for the recorded

@@ -79,6 +79,7 @@ struct TraceStep {
     float theta_max, ds_min, ds_max, eps, ds_uniform, tau;
     int32_t max_steps;
     float near_cap;        // a point closer than this to a face may need the exit clamp
+    float pos_eps;         // rounding margin of coordinates inside the box
 };
 
 struct TraceOutFlat {      // outputs indexed by queue position (ray-subset mode)
@@ -97,7 +98,7 @@ struct TraceLaunch {
     const int64_t *ray_ids;
     TraceOutFlat flat;
     uint32_t *hits;        // compacted slots whose rays enter the volume
-    uint32_t *counters;    // [0] hit count, [1] march queue head
+    uint32_t *counters;    // [0] hit count, [1] head of the dynamic hit batches
     TraceGrid grid;
     TraceStep step;
     int32_t refill_min;    // refill a wave once this many lanes are idle

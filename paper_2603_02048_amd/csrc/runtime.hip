@@ -23,7 +23,9 @@
 
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
-                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, hipStream_t);
+                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, uint32_t *,
+                            hipStream_t);
+int32_t scan_tiles(int32_t ncells);
 hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t);
 hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t);
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
@@ -103,12 +105,15 @@ struct hz_ctx {
     std::atomic<uint64_t> used{0};
     std::mutex ledger_mu;
     // splat scratch
-    Scratch cid, count, start, cursor, slots, sorted, dn;
+    Scratch cid, count, start, cursor, slots, sorted, dn, tiles;
     // trace scratch
     Scratch jobs, hits, counters;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
     int march_bpc[3] = {0, 0, 0};
+    // march tuning (hz_ctx_tune)
+    int32_t refill_min = 16;
+    int32_t blocks_per_cu = 0;   // 0: as many as fit
     std::vector<hz_field *> fields;
     std::mutex fields_mu;
     // memory of released fields, reused in stream order (no host sync)
@@ -371,8 +376,8 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
         for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
         c->prof_free.clear();
     }
-    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->jobs, &c->hits,
-                       &c->counters})
+    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->jobs,
+                       &c->hits, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
         if (p.used && p.done) (void)hipEventSynchronize(p.done);
@@ -380,6 +385,22 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
         if (p.done) (void)hipEventDestroy(p.done);
     }
     delete c;
+}
+
+extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
+{
+    if (!c || !key) return fail(HZ_E_INVALID, "hz_ctx_tune: NULL argument");
+    const std::string k(key);
+    if (k == "march.refill_min") {
+        if (value < 1 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.refill_min must be in [1, 64]");
+        c->refill_min = (int32_t)value;
+    } else if (k == "march.blocks_per_cu") {
+        if (value < 0 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.blocks_per_cu must be in [0, 64]");
+        c->blocks_per_cu = (int32_t)value;
+    } else {
+        return fail(HZ_E_INVALID, "hz_ctx_tune: unknown key '%s'", key);
+    }
+    return HZ_OK;
 }
 
 extern "C" hz_status hz_ctx_memory(const hz_ctx *c, uint64_t *used_bytes, uint64_t *budget_bytes)
@@ -547,10 +568,11 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     hipStream_t s = (hipStream_t)hip_stream;
     const int32_t n = (int32_t)P->n;
     const int64_t nv = (int64_t)g->res[0] * g->res[1] * g->res[2];
-    Scratch *bufs[7] = {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn};
-    const size_t sizes[7] = {4u * (size_t)n, 4u * (size_t)(ncells + 1), 4u * (size_t)(ncells + 1),
-                             4u * (size_t)(ncells + 1), 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv};
-    for (int i = 0; i < 7; ++i) {
+    Scratch *bufs[8] = {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles};
+    const size_t sizes[8] = {4u * (size_t)n, 4u * (size_t)(ncells + 1), 4u * (size_t)(ncells + 1),
+                             4u * (size_t)(ncells + 1), 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv,
+                             4u * (size_t)scan_tiles((int32_t)ncells)};
+    for (int i = 0; i < 8; ++i) {
         st = scratch_acquire(c, *bufs[i], sizes[i], s);
         if (st != HZ_OK) return st;
     }
@@ -561,7 +583,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     hipEvent_t t0 = prof_begin(c, s);
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     (uint32_t *)c->start.ptr, (uint32_t *)c->cursor.ptr, (uint32_t *)c->slots.ptr,
-                                    (float4 *)c->sorted.ptr, s);
+                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, s);
     prof_end(c, s, "cell_list", t0);
     if (e == hipSuccess) {
         hipEvent_t t1 = prof_begin(c, s);
@@ -577,7 +599,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         field_destroy(f);
         return st;
     }
-    for (int i = 0; i < 7; ++i) scratch_release(*bufs[i], s);
+    for (int i = 0; i < 8; ++i) scratch_release(*bufs[i], s);
     field_mark_used(f, s);
     register_field(c, f);
     *out = f;
@@ -737,7 +759,7 @@ void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G)
     G->inv_scale = 1.0f / store_scale;
 }
 
-void make_trace_step(const hz_step &st, TraceStep *S)
+void make_trace_step(const hz_step &st, const hz_grid &g, TraceStep *S)
 {
     S->uniform = st.uniform ? 1 : 0;
     S->theta_max = st.theta_max;
@@ -747,8 +769,12 @@ void make_trace_step(const hz_step &st, TraceStep *S)
     S->ds_uniform = st.ds_uniform;
     S->tau = st.tau_term;
     S->max_steps = st.max_steps;
+    // rounding margin: 8 ulps of the largest coordinate of the box
+    double amax = 0.0;
+    for (int a = 0; a < 3; ++a) amax = std::max(amax, std::max(std::fabs(g.lo[a]), std::fabs(g.hi[a])));
+    S->pos_eps = (float)(8.0 * amax * 1.1920928955078125e-7);
     const float cap = std::max(st.uniform ? st.ds_uniform : st.ds_max, st.tau_term);
-    S->near_cap = cap * 1.001f + 1e-30f;
+    S->near_cap = cap * 1.001f + 2.0f * S->pos_eps;
 }
 
 }  // namespace haze
@@ -817,8 +843,8 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
             J.status = out->status ? out->status + base : nullptr;
         }
     make_trace_grid(f->grid, f->store_scale, &L.grid);
-    make_trace_step(*step, &L.step);
-    L.refill_min = 16;
+    make_trace_step(*step, f->grid, &L.step);
+    L.refill_min = c->refill_min;
     if (L.nslots == 0) return HZ_OK;
 
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -834,8 +860,12 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
     L.hits = (uint32_t *)c->hits.ptr;
     L.counters = (uint32_t *)c->counters.ptr;
     const int dt = (int)f->dtype;
+    // persistent grid: what fits on the chip at once
     const int64_t want_blocks = (L.nslots + 255) / 256;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(want_blocks, (int64_t)c->march_bpc[dt] * c->num_cus));
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, c->march_bpc[dt]) : c->march_bpc[dt];
+    int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
+    blocks64 = std::max<int64_t>(1, blocks64);
+    const int blocks = (int)blocks64;
     hipEvent_t t0 = prof_begin(c, s);
     HZ_HIP(launch_raygen(L, s), "raygen launch");
     prof_end(c, s, "raygen", t0);

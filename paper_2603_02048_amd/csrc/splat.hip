@@ -8,7 +8,8 @@
 // Pipeline (all integer work exact, so the result is bitwise repeatable):
 //   k_cell_count   particle -> cell id (cells of edge h over the grid box grown
 //                  by 2h), integer histogram with atomics
-//   k_scan_cells   exclusive prefix sum of the histogram (one workgroup)
+//   k_scan_*       exclusive prefix sum of the histogram (tile sums, scan of
+//                  the tile sums, tiles rescanned with their offsets)
 //   k_cell_scatter particle index -> a slot of its cell (arbitrary order)
 //   k_cell_order   per cell, rank the slots by particle index (stable order)
 //                  and gather (x, y, z, m) into cell-sorted float4 records
@@ -55,33 +56,83 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
     cid[i] = id;
 }
 
-// Exclusive scan of count[0..n) into start[0..n]; start[n] = total.  One
-// workgroup of 1024 threads; thread t owns a contiguous chunk.
-__global__ __launch_bounds__(1024) void k_scan_cells(const uint32_t *__restrict__ count, uint32_t *__restrict__ start,
-                                                     int32_t n)
+// Exclusive scan of count[0..n) into start[0..n] (start[n] = total) in three
+// passes over tiles of SCAN_TILE cells: tile sums, scan of the tile sums (one
+// workgroup), then each tile rescanned with its offset.
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
+
+// Inclusive scan of one value per thread across a 256-thread workgroup.
+__device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *wave_tot)
 {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int chunk = (n + 1023) / 1024;
-    const int b = t * chunk;
-    const int e = min(n, b + chunk);
-    uint32_t s = 0;
-    for (int i = b; i < e; ++i) s += count[i];
-    part[t] = s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    if (lane == 63) wave_tot[wave] = v;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 chunk sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? part[t - off] : 0u;
+    uint32_t add = 0;
+    for (int w = 0; w < wave; ++w) add += wave_tot[w];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const uint32_t *__restrict__ count, int32_t n,
+                                                             uint32_t *__restrict__ tile_sum)
+{
+    __shared__ uint32_t wt[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k)
+        if (base + k < n) s += count[base + k];
+    const uint32_t incl = block_scan_incl(s, wt);
+    if (threadIdx.x == SCAN_THREADS - 1) tile_sum[blockIdx.x] = incl;
+}
+
+// Exclusive scan of the tile sums in place (one workgroup); writes the grand
+// total to *total.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(uint32_t *__restrict__ tile_sum, int32_t ntiles,
+                                                                 uint32_t *__restrict__ total)
+{
+    __shared__ uint32_t wt[4];
+    __shared__ uint32_t chunk_total;
+    uint32_t carry = 0;
+    for (int32_t b = 0; b < ntiles; b += SCAN_THREADS) {
+        const int32_t i = b + (int32_t)threadIdx.x;
+        const uint32_t v = i < ntiles ? tile_sum[i] : 0u;
+        const uint32_t incl = block_scan_incl(v, wt);
+        if (i < ntiles) tile_sum[i] = carry + incl - v;
+        if (threadIdx.x == SCAN_THREADS - 1) chunk_total = incl;
         __syncthreads();
-        part[t] += v;
+        carry += chunk_total;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;
-    for (int i = b; i < e; ++i) {
-        start[i] = run;
-        run += count[i];
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *__restrict__ count, int32_t n,
+                                                             const uint32_t *__restrict__ tile_off,
+                                                             uint32_t *__restrict__ start)
+{
+    __shared__ uint32_t wt[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        v[k] = base + k < n ? count[base + k] : 0u;
+        s += v[k];
     }
-    if (t == 1023) start[n] = part[1023];
+    uint32_t run = tile_off[blockIdx.x] + block_scan_incl(s, wt) - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (base + k < n) start[base + k] = run;
+        run += v[k];
+    }
 }
 
 // Every binned particle takes a slot of its cell.
@@ -204,20 +255,21 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t rx, int32_t ry, int32_t rz,
                                                    float ix, float iy, float iz, float scale, void *__restrict__ out)
 {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nv = (int64_t)rx * ry * rz;
-    if (v >= nv) return;
-    const int32_t i = (int32_t)(v % rx);
-    const int32_t j = (int32_t)((v / rx) % ry);
-    const int32_t k = (int32_t)(v / ((int64_t)rx * ry));
-    const int64_t sy = rx, sz = (int64_t)rx * ry;
+    // voxel counts are below 2^31 (checked on the host): 32-bit index math
+    const int32_t v = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if ((int64_t)v >= (int64_t)rx * ry * rz) return;
+    const int32_t ij = v / rx;
+    const int32_t i = v - ij * rx;
+    const int32_t k = ij / ry;
+    const int32_t j = ij - k * ry;
+    const int32_t sy = rx, sz = rx * ry;
     const float c = dn[v];
     float g[3];
     {
         // inside: (f[i+1] - f[i-1]) / (2 d); faces: one-sided first difference
         const int32_t idx[3] = {i, j, k};
         const int32_t R[3] = {rx, ry, rz};
-        const int64_t st[3] = {1, sy, sz};
+        const int32_t st[3] = {1, sy, sz};
         const float inv[3] = {ix, iy, iz};
         for (int a = 0; a < 3; ++a) {
             if (idx[a] == 0)
@@ -283,14 +335,20 @@ __global__ __launch_bounds__(256) void k_field_unpack(const void *__restrict__ i
 
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+int32_t scan_tiles(int32_t ncells) { return (ncells + SCAN_TILE - 1) / SCAN_TILE; }
+
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *cursor,
-                            uint32_t *slots, float4 *sorted, hipStream_t s)
+                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 1, 256)), dim3(256), 0, s, count, 0u,
                        (int64_t)cg.ncells + 1);
     hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, n, cg, cid, count);
-    hipLaunchKernelGGL(k_scan_cells, dim3(1), dim3(1024), 0, s, count, start, cg.ncells);
+    const int32_t ntiles = (cg.ncells + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles, start + cg.ncells);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum,
+                       start);
     hipError_t e = hipMemcpyAsync(cursor, start, sizeof(uint32_t) * (size_t)cg.ncells, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, n, cursor, slots);

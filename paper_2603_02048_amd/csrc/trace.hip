@@ -44,6 +44,8 @@ struct Ray {
 // padding slots of partial 8x8 tiles.
 __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, Ray &r)
 {
+    // all slot and ray counts are below 2^31 (checked on the host): 32-bit
+    // division from here on
     if (L.subset) {
         const int64_t id = L.ray_ids[slot];
         int lo = 0, hi = L.njobs - 1;
@@ -55,12 +57,14 @@ __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, 
                 hi = mid - 1;
         }
         const TraceJob &J = L.jobs[lo];
-        const int64_t local = id - J.ray_begin;
+        const int64_t local64 = id - J.ray_begin;
+        if (local64 < 0 || local64 >= (int64_t)J.width * J.height) return false;
+        const int32_t local = (int32_t)local64;
         r.job = lo;
-        r.p = (int32_t)(local % J.width);
-        r.q = (int32_t)(local / J.width);
+        r.q = local / J.width;
+        r.p = local - r.q * J.width;
         r.out = slot;
-        return local >= 0 && r.q < J.height;
+        return true;
     }
     int lo = 0, hi = L.njobs - 1;
     while (lo < hi) {
@@ -71,13 +75,14 @@ __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, 
             hi = mid - 1;
     }
     const TraceJob &J = L.jobs[lo];
-    const int64_t local = slot - J.slot_begin;
-    const int64_t tile = local >> 6;
-    const int32_t within = (int32_t)(local & 63);
+    const int32_t local = (int32_t)(slot - J.slot_begin);
+    const int32_t tile = local >> 6;
+    const int32_t within = local & 63;
+    const int32_t ty = tile / J.tiles_x;
     r.job = lo;
-    r.p = (int32_t)(tile % J.tiles_x) * 8 + (within & 7);
-    r.q = (int32_t)(tile / J.tiles_x) * 8 + (within >> 3);
-    r.out = (int64_t)r.q * J.width + r.p;
+    r.p = (tile - ty * J.tiles_x) * 8 + (within & 7);
+    r.q = ty * 8 + (within >> 3);
+    r.out = r.q * J.width + r.p;
     return r.p < J.width && r.q < J.height;
 }
 
@@ -185,6 +190,7 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
     if (stat) stat[o] = (uint8_t)status;
 }
 
+// counters[0]: hit count; counters[1]: head of the dynamic hit batches
 __global__ void k_trace_init(uint32_t *counters)
 {
     if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
@@ -230,42 +236,20 @@ __global__ __launch_bounds__(256) void k_raygen(TraceLaunch L)
     }
 }
 
-template <int DT>
-__device__ __forceinline__ float4 load_voxel(const void *__restrict__ f, int64_t i, float inv_scale)
+__device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
 {
-    if (DT == DT_F32) {
-        return reinterpret_cast<const float4 *>(f)[i];
-    } else {
-        const ushort4 h = reinterpret_cast<const ushort4 *>(f)[i];
-        float4 v;
-        if (DT == DT_F16) {
-            v = make_float4(__half2float(__ushort_as_half(h.x)), __half2float(__ushort_as_half(h.y)),
-                            __half2float(__ushort_as_half(h.z)), __half2float(__ushort_as_half(h.w)));
-        } else {
-            v = make_float4(__uint_as_float((uint32_t)h.x << 16), __uint_as_float((uint32_t)h.y << 16),
-                            __uint_as_float((uint32_t)h.z << 16), __uint_as_float((uint32_t)h.w << 16));
-        }
-        v.x *= inv_scale;
-        v.y *= inv_scale;
-        v.z *= inv_scale;
-        v.w *= inv_scale;
-        return v;
-    }
-}
-
-__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float t)
-{
-    return make_float4(fmaf(t, b.x - a.x, a.x), fmaf(t, b.y - a.y, a.y), fmaf(t, b.z - a.z, a.z),
-                       fmaf(t, b.w - a.w, a.w));
+    v.x = fmaf(wgt, c.x, v.x);
+    v.y = fmaf(wgt, c.y, v.y);
+    v.z = fmaf(wgt, c.z, v.z);
+    v.w = fmaf(wgt, c.w, v.w);
 }
 
 // Trilinear (delta_n, g) at x: cell index clamped to [0, R-2], so the outer
 // half-voxel extrapolates linearly.
 template <int DT>
-__device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *__restrict__ f, const float x[3])
+__device__ __forceinline__ void cell_of(const TraceGrid &G, const float x[3], int64_t &b, float t[3])
 {
     int32_t i[3];
-    float t[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float u = fmaf(x[a], G.inv_sp[a], G.off[a]);
@@ -273,23 +257,102 @@ __device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *_
         i[a] = (int32_t)fl;
         t[a] = u - fl;
     }
+    b = ((int64_t)i[2] * G.res[1] + i[1]) * G.res[0] + i[0];
+}
+
+// F16/BF16 voxels are 8 bytes; the two x-neighbours of a cell row are one
+// 16-byte load (8-byte aligned, which the hardware serves as one dwordx4).
+typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+// The field pointer reaches the kernel through the job table, so the compiler
+// cannot prove it is global memory; say so, to get global (not flat) loads.
+typedef const u32x4_a8 __attribute__((address_space(1))) *gpair_ptr;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef const f32x4 __attribute__((address_space(1))) *gfloat4_ptr;
+
+__device__ __forceinline__ float4 load_f32x4(gfloat4_ptr F, int64_t i)
+{
+    const f32x4 v = F[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <int DT>
+__device__ __forceinline__ float4 half4_to_float4(uint32_t lo, uint32_t hi)
+{
+    if (DT == DT_F16) {
+        return make_float4(__half2float(__ushort_as_half((unsigned short)(lo & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(lo >> 16))),
+                           __half2float(__ushort_as_half((unsigned short)(hi & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(hi >> 16))));
+    } else {
+        return make_float4(__uint_as_float(lo << 16), __uint_as_float(lo & 0xffff0000u), __uint_as_float(hi << 16),
+                           __uint_as_float(hi & 0xffff0000u));
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void load_xpair(const void *__restrict__ f, int64_t i, float4 &a, float4 &b)
+{
+    const u32x4_a8 v = *(gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * i);
+    a = half4_to_float4<DT>(v.x, v.y);
+    b = half4_to_float4<DT>(v.z, v.w);
+}
+
+template <int DT>
+__device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *__restrict__ f, const float x[3])
+{
+    int64_t b;
+    float t[3];
+    cell_of<DT>(G, x, b, t);
     const int64_t sy = G.res[0], sz = (int64_t)G.res[0] * G.res[1];
-    const int64_t b = ((int64_t)i[2] * G.res[1] + i[1]) * G.res[0] + i[0];
-    const float4 c000 = load_voxel<DT>(f, b, G.inv_scale);
-    const float4 c100 = load_voxel<DT>(f, b + 1, G.inv_scale);
-    const float4 c010 = load_voxel<DT>(f, b + sy, G.inv_scale);
-    const float4 c110 = load_voxel<DT>(f, b + sy + 1, G.inv_scale);
-    const float4 c001 = load_voxel<DT>(f, b + sz, G.inv_scale);
-    const float4 c101 = load_voxel<DT>(f, b + sz + 1, G.inv_scale);
-    const float4 c011 = load_voxel<DT>(f, b + sz + sy, G.inv_scale);
-    const float4 c111 = load_voxel<DT>(f, b + sz + sy + 1, G.inv_scale);
-    const float4 x00 = lerp4(c000, c100, t[0]);
-    const float4 x10 = lerp4(c010, c110, t[0]);
-    const float4 x01 = lerp4(c001, c101, t[0]);
-    const float4 x11 = lerp4(c011, c111, t[0]);
-    const float4 y0 = lerp4(x00, x10, t[1]);
-    const float4 y1 = lerp4(x01, x11, t[1]);
-    return lerp4(y0, y1, t[2]);
+    float4 c000, c100, c010, c110, c001, c101, c011, c111;
+    if (DT == DT_F32) {
+        gfloat4_ptr F = (gfloat4_ptr)f;
+        c000 = load_f32x4(F, b);
+        c100 = load_f32x4(F, b + 1);
+        c010 = load_f32x4(F, b + sy);
+        c110 = load_f32x4(F, b + sy + 1);
+        c001 = load_f32x4(F, b + sz);
+        c101 = load_f32x4(F, b + sz + 1);
+        c011 = load_f32x4(F, b + sz + sy);
+        c111 = load_f32x4(F, b + sz + sy + 1);
+    } else {
+        load_xpair<DT>(f, b, c000, c100);
+        load_xpair<DT>(f, b + sy, c010, c110);
+        load_xpair<DT>(f, b + sz, c001, c101);
+        load_xpair<DT>(f, b + sz + sy, c011, c111);
+    }
+    // trilinear weights, then one FMA per corner and channel
+    const float ux = 1.0f - t[0], uy = 1.0f - t[1], uz = 1.0f - t[2];
+    const float a00 = ux * uy, a10 = t[0] * uy, a01 = ux * t[1], a11 = t[0] * t[1];
+    const float w000 = a00 * uz, w100 = a10 * uz, w010 = a01 * uz, w110 = a11 * uz;
+    const float w001 = a00 * t[2], w101 = a10 * t[2], w011 = a01 * t[2], w111 = a11 * t[2];
+    float4 v;
+    v.x = w000 * c000.x;
+    v.y = w000 * c000.y;
+    v.z = w000 * c000.z;
+    v.w = w000 * c000.w;
+    wsum(v, w100, c100);
+    wsum(v, w010, c010);
+    wsum(v, w110, c110);
+    wsum(v, w001, c001);
+    wsum(v, w101, c101);
+    wsum(v, w011, c011);
+    wsum(v, w111, c111);
+    if (DT != DT_F32) {
+        // stored values are scaled; interpolation is linear, so unscale once
+        v.x *= G.inv_scale;
+        v.y *= G.inv_scale;
+        v.z *= G.inv_scale;
+        v.w *= G.inv_scale;
+    }
+    return v;
+}
+
+// Distance from c to the nearest face of the box (negative outside).
+__device__ __forceinline__ float face_distance(const TraceGrid &G, const float c[3])
+{
+    return fminf(fminf(fminf(c[0] - G.lo[0], G.hi[0] - c[0]), fminf(c[1] - G.lo[1], G.hi[1] - c[1])),
+                 fminf(c[2] - G.lo[2], G.hi[2] - c[2]));
 }
 
 template <int DT>
@@ -301,30 +364,55 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
     const uint32_t refill_min = (uint32_t)max(1, min(64, L.refill_min));
     const int lane = threadIdx.x & 63;
 
+    // Work distribution.  Wave w first takes hits [64 w, 64 w + 64) with no
+    // atomic; later batches of 64 come from one counter past the static range,
+    // fetched one batch ahead (the atomic's latency hides behind the march).
+    // Each wave keeps its reserve [next, end) of hit indices.
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const uint32_t dyn0 = nwaves * 64u;
+    uint32_t next = min(wave_id * 64u, nh);
+    uint32_t end = min(next + 64u, nh);
+    bool done = next >= nh && dyn0 >= nh;
+    bool pending = false;
+    uint32_t pend_v = 0;
+
     bool active = false;
-    bool drained = false;
     Ray r{0, 0, 0, 0};
     const void *field = nullptr;
     // direction omega = p / |p| with p = wr + dw: wr is the entry direction and
     // dw accumulates the turns, so small turns keep their low-order bits
     float c[3] = {0, 0, 0}, cc[3] = {0, 0, 0}, w[3] = {0, 0, 1}, wr[3] = {0, 0, 1}, dw[3] = {0, 0, 0};
     float pnorm = 1.0f;
+    float safe = 0.0f;   // lower bound of the distance from c to the box faces
     uint32_t steps = 0;
 
     for (;;) {
-        uint64_t idle = __ballot(!active);
-        if ((!drained && (uint32_t)__popcll(idle) >= refill_min) || idle == ~0ull) {
-            if (drained) break;
-            const uint32_t nidle = (uint32_t)__popcll(idle);
-            const int leader = __ffsll((unsigned long long)idle) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&L.counters[1], nidle);
-            base = __shfl(base, leader);
-            if (base + nidle >= nh) drained = true;
+        const uint64_t idle = __ballot(!active);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (!done && (nidle >= refill_min || idle == ~0ull)) {
+            if (next == end) {
+                uint32_t b;
+                if (pending) {
+                    b = __shfl(pend_v, 0);
+                    pending = false;
+                } else {
+                    uint32_t v = 0;
+                    if (lane == 0) v = dyn0 + atomicAdd(&L.counters[1], 64u);
+                    b = __shfl(v, 0);
+                }
+                b = __builtin_amdgcn_readfirstlane(b);
+                if (b >= nh) {
+                    done = true;
+                    continue;
+                }
+                next = b;
+                end = min(b + 64u, nh);
+            }
             if (!active) {
-                const uint32_t k = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                const uint32_t k = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-                if (k < nh) {
+                if (k < end) {
                     const int64_t slot = L.hits[k];
                     decode_slot(L, slot, r);
                     const TraceJob &J = L.jobs[r.job];
@@ -340,45 +428,56 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                     c[1] = J.eye[1] + t0 * w[1];
                     c[2] = J.eye[2] + t0 * w[2];
                     cc[0] = cc[1] = cc[2] = 0.0f;
+                    safe = face_distance(G, c);
                     steps = 0;
                     active = true;
                 }
             }
+            next = min(next + nidle, end);
+            if (next == end && !pending) {
+                if (lane == 0) pend_v = dyn0 + atomicAdd(&L.counters[1], 64u);
+                pending = true;
+            }
             continue;
         }
+        if (done && idle == ~0ull) break;
         if (!active) continue;
 
         // ---- one step of Eq. 16 with the step of Eq. 18 ----
-        const float dmin = fminf(fminf(fminf(c[0] - G.lo[0], G.hi[0] - c[0]), fminf(c[1] - G.lo[1], G.hi[1] - c[1])),
-                                 fminf(c[2] - G.lo[2], G.hi[2] - c[2]));
-        const bool near = dmin <= S.near_cap;
-        float te = INFINITY;
         int status = -1;
+        float te = INFINITY;
+        bool near = safe <= S.near_cap;
         if (near) {
-            te = exit_distance(G, c, w);
-            if (te <= S.tau) status = 0;
+            safe = face_distance(G, c);
+            near = safe <= S.near_cap;
+            if (near) {
+                te = exit_distance(G, c, w);
+                if (te <= S.tau) status = 0;
+            }
         }
         if (status < 0) {
             const float4 s = sample_field<DT>(G, field, c);
             const float n = 1.0f + s.x;
+            const float rn = __builtin_amdgcn_rcpf(n);
             const float wg = w[0] * s.y + w[1] * s.z + w[2] * s.w;
             const float pg0 = s.y - wg * w[0], pg1 = s.z - wg * w[1], pg2 = s.w - wg * w[2];
             float ds;
             if (S.uniform) {
                 ds = S.ds_uniform;
             } else {
-                const float pgn = sqrtf(pg0 * pg0 + pg1 * pg1 + pg2 * pg2);
-                ds = fminf(fmaxf(n * S.theta_max / (pgn + S.eps), S.ds_min), S.ds_max);
+                const float pgn = __builtin_amdgcn_sqrtf(pg0 * pg0 + pg1 * pg1 + pg2 * pg2);
+                ds = fminf(fmaxf(n * S.theta_max * __builtin_amdgcn_rcpf(pgn + S.eps), S.ds_min), S.ds_max);
             }
             ds = fminf(ds, te);
             // omega_{k+1} = normalize(omega_k + ds/n P g) = normalize(p + |p| ds/n P g)
-            const float a = ds / n * pnorm;
+            const float a = ds * rn * pnorm;
             dw[0] = fmaf(a, pg0, dw[0]);
             dw[1] = fmaf(a, pg1, dw[1]);
             dw[2] = fmaf(a, pg2, dw[2]);
             const float p0 = wr[0] + dw[0], p1 = wr[1] + dw[1], p2 = wr[2] + dw[2];
-            pnorm = sqrtf(p0 * p0 + p1 * p1 + p2 * p2);
-            const float inv = 1.0f / pnorm;
+            const float pn2 = p0 * p0 + p1 * p1 + p2 * p2;
+            const float inv = __builtin_amdgcn_rsqf(pn2);
+            pnorm = pn2 * inv;
             w[0] = p0 * inv;
             w[1] = p1 * inv;
             w[2] = p2 * inv;
@@ -391,12 +490,13 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                 c[k] = t;
             }
             ++steps;
-            const bool fin = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(w[0]) &&
-                             isfinite(w[1]) && isfinite(w[2]) && isfinite(n);
-            if (!fin)
+            safe -= ds;
+            // any inf or nan among position, direction and n makes the sum non-finite
+            if (!isfinite(c[0] + c[1] + c[2] + w[0] + w[1] + w[2] + n))
                 status = 3;
-            else if (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] || c[2] < G.lo[2] ||
-                     c[2] > G.hi[2])
+            else if (safe <= S.pos_eps &&
+                     (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] || c[2] < G.lo[2] ||
+                      c[2] > G.hi[2]))
                 status = 0;
             else if ((int32_t)steps >= S.max_steps)
                 status = 1;

@@ -62,7 +62,7 @@ class hz_trace_out(C.Structure):
                 ("status", C.c_void_p)]
 
 
-EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_profile_enable",
+EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
            "hz_profile_read", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
@@ -83,6 +83,7 @@ def lib():
         L.hz_ctx_destroy.argtypes, L.hz_ctx_destroy.restype = [P], None
         L.hz_last_error.argtypes, L.hz_last_error.restype = [], C.c_char_p
         L.hz_ctx_memory.argtypes, L.hz_ctx_memory.restype = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], S
+        L.hz_ctx_tune.argtypes, L.hz_ctx_tune.restype = [P, C.c_char_p, C.c_int64], S
         L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
         L.hz_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.hz_profile_read.restype = S
@@ -230,6 +231,9 @@ class Context:
         u, b = C.c_uint64(), C.c_uint64()
         _check(lib().hz_ctx_memory(C.c_void_p(self.handle), C.byref(u), C.byref(b)), "ctx_memory")
         return u.value, b.value
+
+    def tune(self, key: str, value: int):
+        _check(lib().hz_ctx_tune(C.c_void_p(self.handle), key.encode(), int(value)), "ctx_tune")
 
     def profile_enable(self, enable: bool = True):
         _check(lib().hz_profile_enable(C.c_void_p(self.handle), 1 if enable else 0), "profile_enable")
