@@ -151,13 +151,21 @@ static void ledger_give(hz_ctx *c, uint64_t bytes)
     c->used -= std::min<uint64_t>(bytes, c->used.load());
 }
 
+static void pool_trim(hz_ctx *c, size_t need);
+static uint64_t pool_bytes(hz_ctx *c);
+
 namespace haze {
 // Device allocation charged to the context's budget (used by serve.hip too).
+// Pooled memory of released fields is given back first when the budget is
+// short.
 hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes)
 {
-    if (!ledger_take(c, bytes))
-        return fail(HZ_E_BUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu bytes in use)", bytes,
-                    (unsigned long long)c->used.load(), (unsigned long long)c->budget);
+    if (!ledger_take(c, bytes)) {
+        pool_trim(c, bytes);
+        if (!ledger_take(c, bytes))
+            return fail(HZ_E_BUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu bytes in use)",
+                        bytes, (unsigned long long)c->used.load(), (unsigned long long)c->budget);
+    }
     hipError_t e = hipMalloc(p, bytes == 0 ? 256 : bytes);
     if (e != hipSuccess) {
         ledger_give(c, bytes);
@@ -174,6 +182,15 @@ void ctx_free(hz_ctx *c, void *p, size_t bytes)
 }
 
 int ctx_device(const hz_ctx *c) { return c->device; }
+
+// Budget left, counting pooled (released) field memory as available.
+uint64_t ctx_mem_avail(const hz_ctx *c)
+{
+    hz_ctx *cc = const_cast<hz_ctx *>(c);
+    const uint64_t used = c->used.load(), pooled = pool_bytes(cc);
+    const uint64_t held = used > pooled ? used - pooled : 0;
+    return c->budget > held ? c->budget - held : 0;
+}
 int ctx_num_cus(const hz_ctx *c) { return c->num_cus; }
 }  // namespace haze
 
@@ -269,6 +286,7 @@ static void field_recycle(hz_field *f)
 // the budget or the pool is empty.
 static void pool_trim(hz_ctx *c, size_t need)
 {
+    if (need > c->budget) need = c->budget;
     std::lock_guard<std::mutex> g(c->pool_mu);
     while (!c->pool.empty() && c->used.load() + need > c->budget) {
         hz_ctx::PoolBlock b = c->pool.back();
@@ -280,6 +298,14 @@ static void pool_trim(hz_ctx *c, size_t need)
 }
 
 static void pool_free_all(hz_ctx *c) { pool_trim(c, (size_t)-1 / 2); }
+
+static uint64_t pool_bytes(hz_ctx *c)
+{
+    std::lock_guard<std::mutex> g(c->pool_mu);
+    uint64_t b = 0;
+    for (const hz_ctx::PoolBlock &p : c->pool) b += p.bytes;
+    return b;
+}
 
 // ---------------------------------------------------------------------------
 // per-kernel event timing

@@ -14,6 +14,7 @@ hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes);
 void ctx_free(hz_ctx *c, void *p, size_t bytes);
 int ctx_device(const hz_ctx *c);
 int ctx_num_cus(const hz_ctx *c);
+uint64_t ctx_mem_avail(const hz_ctx *c);
 Server *&ctx_server(hz_ctx *c);
 const hz_grid &field_grid(const hz_field *f);
 hz_dtype field_dtype(const hz_field *f);

@@ -1,36 +1,438 @@
-// serve.hip -- serving loop (continuous batching of multi-view requests).
+// serve.hip -- serving loop: continuous batching of multi-view trace requests.
+//
+// hz_submit enqueues a request (views of one field, one step control) and
+// returns at once.  A scheduler thread owns `slots` launch slots, each with
+// its own HIP stream, job table, hit list and counters.  Whenever a slot is
+// free it takes the oldest pending request and every later pending request
+// that can share its launch (same grid, storage type and step control; the
+// fields may differ, e.g. different frames), as long as the batch fits the
+// slot and the requests' output buffers fit the context's HBM budget; the
+// batch is traced by one persistent launch (ray generation + march, the same
+// kernels as hz_trace_views).  Requests arriving while others run are
+// admitted as soon as a slot and memory free up, and launches on different
+// slots overlap on the device.  A request's rays are computed exactly as in a
+// solo hz_trace_views call, whatever else shares the launch.
+#include "haze_device.h"
 #include "serve.h"
+#include "serve_policy.h"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
 
 namespace haze {
-struct Server {
-    int unused;
+hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
+hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t);
+hz_status check_step(const hz_step *st, const char *fn);
+hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
+                   const char *fn, int index);
+void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G);
+void make_trace_step(const hz_step &st, const hz_grid &g, TraceStep *S);
+
+enum ReqState { REQ_PENDING = 0, REQ_RUNNING = 1, REQ_DONE = 2, REQ_FAILED = 3 };
+
+struct Request {
+    hz_ticket id = 0;
+    hz_field *field = nullptr;
+    std::vector<hz_view> views;
+    hz_step step{};
+    BatchKey key = zero_key();
+    int64_t nrays = 0, nslots = 0, out_bytes = 0;
+    void *out_mem = nullptr;
+    hz_trace_out out{};
+    double t_submit = 0.0, t_done = 0.0;
+    int state = REQ_PENDING;
+    hz_status err = HZ_OK;
 };
-void server_destroy(Server *s) { delete s; }
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Request *> reqs;
+    void *jobs = nullptr;       // device job table
+    size_t jobs_cap = 0;
+    void *pinned = nullptr;     // host staging of the job table
+    size_t pinned_cap = 0;
+    void *hits = nullptr;       // u32 per queue slot
+    void *counters = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+struct Server {
+    hz_ctx *ctx = nullptr;
+    int64_t slot_capacity = 0;  // queue slots per launch
+    std::vector<Slot> slots;
+    std::deque<Request *> pending;
+    std::unordered_map<hz_ticket, Request *> reqs;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread th;
+    bool stop = false;
+    hz_ticket next_id = 1;
+    hz_status fatal = HZ_OK;
+};
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static BatchKey make_key(const hz_field *f, const hz_step &st)
+{
+    BatchKey k = zero_key();
+    const hz_grid &g = field_grid(f);
+    for (int a = 0; a < 3; ++a) {
+        k.lo[a] = g.lo[a];
+        k.hi[a] = g.hi[a];
+        k.res[a] = g.res[a];
+    }
+    k.dtype = (int32_t)field_dtype(f);
+    k.store_scale = field_scale(f);
+    k.uniform = st.uniform ? 1 : 0;
+    k.theta_max = st.theta_max;
+    k.ds_min = st.ds_min;
+    k.ds_max = st.ds_max;
+    k.eps = st.eps;
+    k.ds_uniform = st.ds_uniform;
+    k.max_steps = st.max_steps;
+    k.tau_term = st.tau_term;
+    return k;
+}
+
+static void free_outputs(Server *S, Request *r)
+{
+    if (r->out_mem) ctx_free(S->ctx, r->out_mem, (size_t)r->out_bytes);
+    r->out_mem = nullptr;
+}
+
+// Allocate a request's outputs: one buffer carved into the five arrays.
+static hz_status alloc_outputs(Server *S, Request *r)
+{
+    hz_status st = ctx_alloc(S->ctx, &r->out_mem, (size_t)r->out_bytes);
+    if (st != HZ_OK) return st;
+    char *base = (char *)r->out_mem;
+    const int64_t n = r->nrays;
+    r->out.disp = (float *)base;
+    r->out.exit_pos = (float *)(base + 8 * n);
+    r->out.exit_dir = (float *)(base + 20 * n);
+    r->out.steps = (uint32_t *)(base + 32 * n);
+    r->out.status = (uint8_t *)(base + 36 * n);
+    return HZ_OK;
+}
+
+// Launch one batch on a free slot; called with the server lock held.
+static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch)
+{
+    std::vector<TraceJob> jobs;
+    int64_t slot = 0, ray = 0;
+    for (Request *r : batch) {
+        int64_t local_ray = 0;
+        for (size_t i = 0; i < r->views.size(); ++i) {
+            TraceJob J;
+            hz_status st = make_job(&r->views[i], field_data(r->field), slot, ray, &J, "serve", (int)i);
+            if (st != HZ_OK) return st;
+            J.disp = r->out.disp + 2 * local_ray;
+            J.exit_pos = r->out.exit_pos + 3 * local_ray;
+            J.exit_dir = r->out.exit_dir + 3 * local_ray;
+            J.steps = r->out.steps + local_ray;
+            J.status = r->out.status + local_ray;
+            jobs.push_back(J);
+            const int64_t nr = (int64_t)r->views[i].width * r->views[i].height;
+            slot += view_slots(r->views[i].width, r->views[i].height);
+            ray += nr;
+            local_ray += nr;
+        }
+    }
+    const size_t job_bytes = sizeof(TraceJob) * jobs.size();
+    if (sl.jobs_cap < job_bytes) {
+        if (sl.jobs) ctx_free(S->ctx, sl.jobs, sl.jobs_cap);
+        sl.jobs = nullptr;
+        sl.jobs_cap = 0;
+        hz_status st = ctx_alloc(S->ctx, &sl.jobs, job_bytes);
+        if (st != HZ_OK) return st;
+        sl.jobs_cap = job_bytes;
+    }
+    if (sl.pinned_cap < job_bytes) {
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        sl.pinned = nullptr;
+        sl.pinned_cap = 0;
+        if (hipHostMalloc(&sl.pinned, job_bytes, hipHostMallocDefault) != hipSuccess)
+            return set_error(HZ_E_NOMEM, "serve: hipHostMalloc failed");
+        sl.pinned_cap = job_bytes;
+    }
+    // the slot is idle, so its previous copy out of `pinned` has completed
+    std::memcpy(sl.pinned, jobs.data(), job_bytes);
+    if (hipMemcpyAsync(sl.jobs, sl.pinned, job_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        return set_error(HZ_E_DEVICE, "serve: hipMemcpyAsync failed");
+
+    Request *head = batch[0];
+    TraceLaunch L{};
+    L.jobs = (const TraceJob *)sl.jobs;
+    L.njobs = (int32_t)jobs.size();
+    L.subset = 0;
+    L.nslots = slot;
+    L.ray_ids = nullptr;
+    L.hits = (uint32_t *)sl.hits;
+    L.counters = (uint32_t *)sl.counters;
+    make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
+    make_trace_step(head->step, field_grid(head->field), &L.step);
+    L.refill_min = 16;
+    const int dt = (int)field_dtype(head->field);
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
+    hipEvent_t t0 = profile_begin(S->ctx, sl.stream);
+    if (launch_raygen(L, sl.stream) != hipSuccess || launch_march(dt, L, blocks, sl.stream) != hipSuccess)
+        return set_error(HZ_E_DEVICE, "serve: trace launch failed");
+    profile_end(S->ctx, sl.stream, "serve_batch", t0);
+    if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
+    for (Request *r : batch) {
+        field_use(r->field, sl.stream);
+        r->state = REQ_RUNNING;
+    }
+    sl.reqs = batch;
+    sl.busy = true;
+    return HZ_OK;
+}
+
+static void scheduler(Server *S)
+{
+    (void)hipSetDevice(ctx_device(S->ctx));
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        bool progressed = false, any_busy = false;
+        for (Slot &sl : S->slots) {
+            if (!sl.busy) continue;
+            const hipError_t e = hipEventQuery(sl.done);
+            if (e == hipSuccess || e != hipErrorNotReady) {
+                const double t = now_s();
+                for (Request *r : sl.reqs) {
+                    r->t_done = t;
+                    r->state = e == hipSuccess ? REQ_DONE : REQ_FAILED;
+                    if (e != hipSuccess) r->err = HZ_E_DEVICE;
+                }
+                sl.reqs.clear();
+                sl.busy = false;
+                progressed = true;
+            } else {
+                any_busy = true;
+            }
+        }
+        for (Slot &sl : S->slots) {
+            if (sl.busy || S->pending.empty()) continue;
+            std::vector<PendingInfo> info;
+            const size_t window = std::min<size_t>(S->pending.size(), 256);
+            for (size_t i = 0; i < window; ++i)
+                info.push_back({S->pending[i]->key, S->pending[i]->nslots, S->pending[i]->out_bytes});
+            const std::vector<size_t> pick =
+                plan_batch(info, S->slot_capacity, (int64_t)ctx_mem_avail(S->ctx), 256);
+            if (pick.empty()) {
+                // the oldest request waits for memory; when stopping with nothing
+                // running, no memory will come back: fail what is left
+                if (S->stop && !any_busy) {
+                    for (Request *r : S->pending) {
+                        r->state = REQ_FAILED;
+                        r->err = HZ_E_BUDGET;
+                        r->t_done = now_s();
+                    }
+                    S->pending.clear();
+                }
+                break;
+            }
+            std::vector<Request *> batch;
+            for (size_t i : pick) {
+                Request *r = S->pending[i];
+                if (alloc_outputs(S, r) != HZ_OK) break;   // memory went away: launch what we have
+                batch.push_back(r);
+            }
+            if (batch.empty()) break;
+            // remove the launched requests from the pending queue (keep order of the rest)
+            std::deque<Request *> rest;
+            for (Request *r : S->pending)
+                if (std::find(batch.begin(), batch.end(), r) == batch.end()) rest.push_back(r);
+            S->pending.swap(rest);
+            const hz_status st = launch_batch(S, sl, batch);
+            if (st != HZ_OK) {
+                for (Request *r : batch) {
+                    r->state = REQ_FAILED;
+                    r->err = st;
+                    r->t_done = now_s();
+                }
+            } else {
+                any_busy = true;
+            }
+            progressed = true;
+        }
+        if (S->stop && S->pending.empty() && !any_busy) break;
+        if (!progressed) S->cv.wait_for(lk, any_busy ? std::chrono::microseconds(20) : std::chrono::milliseconds(2));
+    }
+}
+
+void server_destroy(Server *S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    for (Slot &sl : S->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.jobs) ctx_free(S->ctx, sl.jobs, sl.jobs_cap);
+        if (sl.hits) ctx_free(S->ctx, sl.hits, sl.scratch_bytes);
+        if (sl.counters) ctx_free(S->ctx, sl.counters, 256);
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    for (auto &kv : S->reqs) {
+        free_outputs(S, kv.second);
+        delete kv.second;
+    }
+    delete S;
+}
+
 }  // namespace haze
 
 using namespace haze;
 
-extern "C" hz_status hz_server_start(hz_ctx *, int32_t, int64_t)
+extern "C" hz_status hz_server_start(hz_ctx *c, int32_t nslots, int64_t max_batch_rays)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_server_start: serving not built yet");
+    if (!c) return set_error(HZ_E_INVALID, "hz_server_start: ctx is NULL");
+    if (nslots < 1 || nslots > 16) return set_error(HZ_E_INVALID, "hz_server_start: slots must be in [1, 16]");
+    if (max_batch_rays < 1 || max_batch_rays > INT32_MAX / 2)
+        return set_error(HZ_E_INVALID, "hz_server_start: max_batch_rays must be in [1, 2^30]");
+    if (ctx_server(c)) return set_error(HZ_E_INVALID, "hz_server_start: the server is already running");
+    if (hipSetDevice(ctx_device(c)) != hipSuccess) return set_error(HZ_E_DEVICE, "hz_server_start: hipSetDevice");
+    Server *S = new Server();
+    S->ctx = c;
+    S->slot_capacity = (max_batch_rays + 63) / 64 * 64;
+    S->slots.resize((size_t)nslots);
+    for (Slot &sl : S->slots) {
+        sl.scratch_bytes = 4u * (size_t)S->slot_capacity;
+        hz_status st = ctx_alloc(c, &sl.hits, sl.scratch_bytes);
+        if (st == HZ_OK) st = ctx_alloc(c, &sl.counters, 256);
+        if (st == HZ_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
+            st = set_error(HZ_E_DEVICE, "hz_server_start: hipStreamCreate failed");
+        if (st == HZ_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+            st = set_error(HZ_E_DEVICE, "hz_server_start: hipEventCreate failed");
+        if (st != HZ_OK) {
+            server_destroy(S);
+            return st;
+        }
+    }
+    ctx_server(c) = S;
+    S->th = std::thread(scheduler, S);
+    return HZ_OK;
 }
-extern "C" hz_status hz_submit(hz_ctx *, const hz_field *, const hz_view *, int32_t, const hz_step *, hz_ticket *)
+
+extern "C" hz_status hz_server_stop(hz_ctx *c)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_submit: serving not built yet");
+    if (!c) return set_error(HZ_E_INVALID, "hz_server_stop: ctx is NULL");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_server_stop: no server running");
+    server_destroy(S);
+    ctx_server(c) = nullptr;
+    return HZ_OK;
 }
-extern "C" hz_status hz_poll(hz_ctx *, hz_ticket, double *)
+
+extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
+                               const hz_step *step, hz_ticket *out)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_poll: serving not built yet");
+    const char *fn = "hz_submit";
+    if (!c || !f || !views || !out) return set_error(HZ_E_INVALID, "hz_submit: NULL argument");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_submit: no server running (hz_server_start)");
+    if (field_ctx(f) != c) return set_error(HZ_E_INVALID, "hz_submit: field belongs to another context");
+    if (nviews < 1 || nviews > 4096) return set_error(HZ_E_INVALID, "hz_submit: nviews outside [1, 4096]");
+    hz_status st = check_step(step, fn);
+    if (st != HZ_OK) return st;
+    Request *r = new Request();
+    r->field = const_cast<hz_field *>(f);
+    r->views.assign(views, views + nviews);
+    r->step = *step;
+    for (int i = 0; i < nviews; ++i) {
+        TraceJob J;
+        st = make_job(&views[i], field_data(f), 0, 0, &J, fn, i);
+        if (st != HZ_OK) {
+            delete r;
+            return st;
+        }
+        r->nrays += (int64_t)views[i].width * views[i].height;
+        r->nslots += view_slots(views[i].width, views[i].height);
+    }
+    r->out_bytes = r->nrays * kOutBytesPerRay;
+    r->key = make_key(f, *step);
+    uint64_t budget = 0;
+    hz_ctx_memory(c, nullptr, &budget);
+    if (r->nslots > S->slot_capacity || (uint64_t)r->out_bytes > budget) {
+        delete r;
+        return set_error(HZ_E_BUDGET, "hz_submit: the request exceeds the batch capacity or the HBM budget");
+    }
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        r->id = S->next_id++;
+        r->t_submit = now_s();
+        S->reqs[r->id] = r;
+        S->pending.push_back(r);
+        *out = r->id;
+    }
+    S->cv.notify_all();
+    return HZ_OK;
 }
-extern "C" hz_status hz_request_outputs(hz_ctx *, hz_ticket, hz_trace_out *, int64_t *)
+
+extern "C" hz_status hz_poll(hz_ctx *c, hz_ticket t, double *latency_s)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_request_outputs: serving not built yet");
+    if (!c) return set_error(HZ_E_INVALID, "hz_poll: ctx is NULL");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_poll: no server running");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return set_error(HZ_E_NOTFOUND, "hz_poll: unknown ticket");
+    Request *r = it->second;
+    if (r->state == REQ_FAILED) return set_error(r->err, "hz_poll: the request failed");
+    if (r->state != REQ_DONE) return HZ_PENDING;
+    if (latency_s) *latency_s = r->t_done - r->t_submit;
+    return HZ_OK;
 }
-extern "C" hz_status hz_request_release(hz_ctx *, hz_ticket)
+
+extern "C" hz_status hz_request_outputs(hz_ctx *c, hz_ticket t, hz_trace_out *out, int64_t *nrays)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_request_release: serving not built yet");
+    if (!c || !out) return set_error(HZ_E_INVALID, "hz_request_outputs: NULL argument");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_request_outputs: no server running");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return set_error(HZ_E_NOTFOUND, "hz_request_outputs: unknown ticket");
+    Request *r = it->second;
+    if (r->state != REQ_DONE) return set_error(HZ_E_INVALID, "hz_request_outputs: the request is not complete");
+    *out = r->out;
+    if (nrays) *nrays = r->nrays;
+    return HZ_OK;
 }
-extern "C" hz_status hz_server_stop(hz_ctx *)
+
+extern "C" hz_status hz_request_release(hz_ctx *c, hz_ticket t)
 {
-    return set_error(HZ_E_UNSUPPORTED, "hz_server_stop: serving not built yet");
+    if (!c) return set_error(HZ_E_INVALID, "hz_request_release: ctx is NULL");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_request_release: no server running");
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        auto it = S->reqs.find(t);
+        if (it == S->reqs.end()) return set_error(HZ_E_NOTFOUND, "hz_request_release: unknown ticket");
+        Request *r = it->second;
+        if (r->state == REQ_RUNNING) return set_error(HZ_E_INVALID, "hz_request_release: the request is running");
+        if (r->state == REQ_PENDING) S->pending.erase(std::find(S->pending.begin(), S->pending.end(), r));
+        free_outputs(S, r);
+        S->reqs.erase(it);
+        delete r;
+    }
+    S->cv.notify_all();   // freed memory may admit a waiting request
+    return HZ_OK;
 }

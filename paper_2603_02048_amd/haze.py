@@ -306,13 +306,14 @@ class Context:
         s = _check(lib().hz_poll(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(lat)), "poll")
         return None if s == PENDING else lat.value
 
-    def request_outputs(self, ticket: int) -> dict:
-        """Copies of a completed request's outputs (torch tensors on the GPU)."""
+    def request_outputs(self, ticket: int, copy: bool = True) -> dict:
+        """A completed request's outputs as torch tensors on the GPU (copies by
+        default; with copy=False, views valid until request_release)."""
         o = hz_trace_out()
         n = C.c_int64()
         _check(lib().hz_request_outputs(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(o), C.byref(n)),
                "request_outputs")
-        return _wrap_device_outputs(o, n.value)
+        return _wrap_device_outputs(o, n.value, copy)
 
     def request_release(self, ticket: int):
         _check(lib().hz_request_release(C.c_void_p(self.handle), C.c_uint64(ticket)), "request_release")
@@ -329,27 +330,21 @@ def alloc_outputs(n: int, device="cuda") -> dict:
                 status=torch.empty(n, dtype=torch.uint8, device=device))
 
 
-def _wrap_device_outputs(o: hz_trace_out, n: int) -> dict:
-    """Copy library-owned device arrays into fresh torch tensors (device to device)."""
-    out = alloc_outputs(n)
-    spec = [("disp", o.disp, 8), ("exit_pos", o.exit_pos, 12), ("exit_dir", o.exit_dir, 12), ("steps", o.steps, 4),
-            ("status", o.status, 1)]
-    hip = _hip_runtime()
-    for name, src, per in spec:
-        if src and n:
-            rc = hip.hipMemcpy(C.c_void_p(out[name].data_ptr()), C.c_void_p(src), C.c_size_t(per * n), 3)
-            if rc != 0:
-                raise HazeError(E_DEVICE, f"hipMemcpy of request outputs failed ({rc})")
+class _DeviceArray:
+    """Zero-copy view of library-owned device memory (CUDA array interface)."""
+
+    def __init__(self, ptr: int, shape: tuple, typestr: str):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": shape, "typestr": typestr,
+                                         "version": 2, "strides": None}
+
+
+def _wrap_device_outputs(o: hz_trace_out, n: int, copy: bool = True) -> dict:
+    """Torch tensors over a request's library-owned outputs (cloned by default,
+    since the library frees them at request_release)."""
+    spec = [("disp", o.disp, (n, 2), "<f4"), ("exit_pos", o.exit_pos, (n, 3), "<f4"),
+            ("exit_dir", o.exit_dir, (n, 3), "<f4"), ("steps", o.steps, (n,), "<i4"), ("status", o.status, (n,), "|u1")]
+    out = {}
+    for name, ptr, shape, ts in spec:
+        t = torch.as_tensor(_DeviceArray(ptr, shape, ts), device="cuda")
+        out[name] = t.clone() if copy else t
     return out
-
-
-_hip = None
-
-
-def _hip_runtime():
-    global _hip
-    if _hip is None:
-        _hip = C.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
-        _hip.hipMemcpy.restype = C.c_int
-    return _hip

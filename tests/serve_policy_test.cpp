@@ -1,0 +1,72 @@
+// CPU test of the serving loop's batching policy (serve_policy.h).
+#include "serve_policy.h"
+
+#include <cstdio>
+#include <cstdlib>
+
+using namespace haze;
+
+static int failures = 0;
+#define CHECK(cond)                                                        \
+    do {                                                                   \
+        if (!(cond)) {                                                     \
+            std::printf("FAIL %s:%d: %s\n", __FILE__, __LINE__, #cond);    \
+            ++failures;                                                    \
+        }                                                                  \
+    } while (0)
+
+static PendingInfo req(int key, int64_t slots, int64_t bytes)
+{
+    PendingInfo p;
+    p.key = zero_key();
+    p.key.res[0] = key;   // requests with equal `key` share launches
+    p.slots = slots;
+    p.out_bytes = bytes;
+    return p;
+}
+
+int main()
+{
+    // empty queue
+    CHECK(plan_batch({}, 100, 100, 8).empty());
+    // the oldest request leads; compatible followers join in order
+    {
+        std::vector<PendingInfo> q = {req(1, 10, 10), req(2, 10, 10), req(1, 20, 20), req(1, 30, 30)};
+        auto p = plan_batch(q, 100, 1000, 8);
+        CHECK(p.size() == 3 && p[0] == 0 && p[1] == 2 && p[2] == 3);
+    }
+    // slot capacity: a follower that would overflow is skipped, a later smaller one joins
+    {
+        std::vector<PendingInfo> q = {req(1, 60, 1), req(1, 50, 1), req(1, 30, 1)};
+        auto p = plan_batch(q, 100, 1000, 8);
+        CHECK(p.size() == 2 && p[0] == 0 && p[1] == 2);
+    }
+    // memory admission: the head waits when its outputs do not fit
+    {
+        std::vector<PendingInfo> q = {req(1, 10, 500), req(1, 10, 10)};
+        CHECK(plan_batch(q, 100, 400, 8).empty());
+        auto p = plan_batch(q, 100, 505, 8);
+        CHECK(p.size() == 1 && p[0] == 0);
+        p = plan_batch(q, 100, 510, 8);
+        CHECK(p.size() == 2);
+    }
+    // a head larger than a launch can never run in this slot
+    {
+        std::vector<PendingInfo> q = {req(1, 200, 1)};
+        CHECK(plan_batch(q, 100, 1000, 8).empty());
+    }
+    // request cap per launch
+    {
+        std::vector<PendingInfo> q;
+        for (int i = 0; i < 20; ++i) q.push_back(req(3, 1, 1));
+        CHECK(plan_batch(q, 100, 1000, 5).size() == 5);
+    }
+    // slot counting: 8x8 tiles of 64 slots, ragged edges padded
+    CHECK(view_slots(8, 8) == 64);
+    CHECK(view_slots(9, 8) == 128);
+    CHECK(view_slots(1280, 720) == 1280 * 720);
+    CHECK(view_slots(37, 23) == 5 * 3 * 64);
+    CHECK(kOutBytesPerRay == 37);
+    std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
+    return failures ? 1 : 0;
+}

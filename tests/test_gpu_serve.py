@@ -1,0 +1,137 @@
+"""Serving loop on the GPU: continuous batching of mixed multi-view requests.
+
+Every request's outputs must be bitwise identical to a solo hz_trace_views of
+the same views, however the scheduler batched it; admission waits for HBM
+budget; errors are reported per ticket.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_02048_amd import workloads as W
+from tests.parity import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def haze():
+    from paper_2603_02048_amd import haze as h
+    h.lib()
+    return h
+
+
+def _wait(ctx, tickets, timeout=60.0):
+    lat = {}
+    t0 = time.time()
+    while len(lat) < len(tickets):
+        for t in tickets:
+            if t not in lat:
+                v = ctx.poll(t)
+                if v is not None:
+                    lat[t] = v
+        assert time.time() - t0 < timeout, "requests did not complete"
+        time.sleep(0.001)
+    return lat
+
+
+def _frames(ctx, haze, n=3):
+    fields = []
+    for k in range(n):
+        wl = W.make_small(seed=10 + k, n=4000, width=8, height=8, nviews=1).with_k_gd(150.0)
+        fields.append((wl, ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)))
+    return fields
+
+
+def _random_request(rng, grid):
+    sizes = [(37, 23), (64, 40), (20, 12), (8, 8)]
+    nv = int(rng.integers(1, 4))
+    w, h = sizes[int(rng.integers(0, len(sizes)))]
+    radius = float(rng.uniform(0.9, 1.6))
+    az0 = float(rng.uniform(0, 2 * np.pi))
+    return [W.ring_view(grid.lo, grid.hi, az0 + 2 * np.pi * k / nv, radius, w, h, backdrop_beyond=0.6)
+            for k in range(nv)]
+
+
+def test_serve_mix_equals_solo(haze):
+    ctx = haze.Context(0)
+    try:
+        frames = _frames(ctx, haze)
+        grid = frames[0][0].grid
+        st_a, st_u = W.make_steps(grid)
+        ctx.server_start(slots=3, max_batch_rays=1 << 16)
+        rng = np.random.default_rng(0)
+        reqs = []
+        for i in range(24):
+            fi = int(rng.integers(0, len(frames)))
+            views = _random_request(rng, grid)
+            st = st_a if rng.random() < 0.7 else st_u
+            t = ctx.submit(frames[fi][1], views, st)
+            reqs.append((t, fi, views, st))
+            if i % 5 == 4:
+                time.sleep(0.002)   # some requests arrive while others run
+        lat = _wait(ctx, [r[0] for r in reqs])
+        assert all(v > 0 for v in lat.values())
+        for t, fi, views, st in reqs:
+            got = to_np(ctx.request_outputs(t))
+            solo = to_np(ctx.trace_views(frames[fi][1], views, st))
+            torch.cuda.synchronize()
+            for k in solo:
+                assert np.array_equal(got[k].view(np.uint8), solo[k].view(np.uint8)), (t, k)
+            assert (got["steps"] > 0).any()
+            ctx.request_release(t)
+        ms, n = ctx.profile_read("serve_batch")
+        print(f"serve: {len(reqs)} requests, latency p50 {np.percentile(list(lat.values()), 50) * 1e3:.2f} ms, "
+              f"max {max(lat.values()) * 1e3:.2f} ms", flush=True)
+        ctx.server_stop()
+    finally:
+        ctx.close()
+
+
+def test_serve_budget_admission_and_errors(haze):
+    wl = W.make_small(seed=3, n=3000, width=8, height=8, nviews=1)
+    # budget: the field, one launch slot's scratch and outputs for ~1.5 requests
+    views = [W.ring_view(wl.grid.lo, wl.grid.hi, 0.3, 1.2, 256, 128)]
+    per_req = 256 * 128 * 37
+    probe = haze.Context(0)
+    f0 = probe.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
+    used_with_field, _ = probe.memory()
+    probe.close()
+    max_batch = 256 * 128
+    budget = used_with_field + 4 * max_batch + 256 + 64 * 1024 + int(1.5 * per_req)
+    ctx = haze.Context(0, budget_bytes=budget)
+    try:
+        f = ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
+        with pytest.raises(haze.HazeError) as e:
+            ctx.submit(f, views, wl.step_adaptive)
+        assert e.value.status == haze.E_INVALID          # no server yet
+        ctx.server_start(slots=1, max_batch_rays=max_batch)
+        big = [W.ring_view(wl.grid.lo, wl.grid.hi, 0.3, 1.2, 512, 512)]
+        with pytest.raises(haze.HazeError) as e:
+            ctx.submit(f, big, wl.step_adaptive)        # larger than a launch
+        assert e.value.status == haze.E_BUDGET
+        with pytest.raises(haze.HazeError) as e:
+            ctx.poll(987654321)
+        assert e.value.status == haze.E_NOTFOUND
+        tickets = [ctx.submit(f, views, wl.step_adaptive) for _ in range(3)]
+        done = _wait(ctx, tickets[:1])
+        time.sleep(0.05)
+        # the second request cannot get output memory while the first holds it
+        assert ctx.poll(tickets[1]) is None
+        first = to_np(ctx.request_outputs(tickets[0]))
+        ctx.request_release(tickets[0])
+        _wait(ctx, tickets[1:2])
+        ctx.request_release(tickets[1])
+        _wait(ctx, tickets[2:3])
+        last = to_np(ctx.request_outputs(tickets[2]))
+        for k in first:
+            assert np.array_equal(first[k].view(np.uint8), last[k].view(np.uint8))
+        ctx.request_release(tickets[2])
+        with pytest.raises(haze.HazeError) as e:
+            ctx.request_release(tickets[2])
+        assert e.value.status == haze.E_NOTFOUND
+        ctx.server_stop()
+    finally:
+        ctx.close()
