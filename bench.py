@@ -32,6 +32,9 @@ if ROOT not in sys.path:
 
 METRIC = "rays/s & ray-steps/s, adaptive vs uniform step, 1 MI355X; p50/p99 view latency"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions (the kernels are built with
+# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
 BYTES_PER_STEP = {"f32": 128, "f16": 64, "bf16": 64}   # 8 corners x 4 channels
 
 
@@ -84,6 +87,73 @@ def count_pairs(torch, parts, grid, h: float) -> int:
     return total
 
 
+def pipelined(ctx, torch, make_step_on, steps: int, warmup: int) -> float:
+    """ms per frame when frame i+1's splat overlaps frame i's trace (two streams)."""
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for i in range(warmup):
+        make_step_on(streams[i % 2], i % 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        make_step_on(streams[i % 2], i % 2)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def serving_leg(haze, torch, W, args) -> dict:
+    """Config 5: resident per-frame F16 fields, Poisson requests at 200/s."""
+    wl = W.make_config(5)
+    ctx = haze.Context(0)
+    try:
+        fields = []
+        for fr in W.advect_frames(wl.particles, wl.grid.lo, wl.grid.hi, nframes=args.serve_frames, device="cuda"):
+            parts = haze.upload_particles(fr)
+            fields.append(ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype="f16", store_scale=1e4))
+        torch.cuda.synchronize()
+        reqs = W.serving_requests(wl.grid.lo, wl.grid.hi, args.serve_seconds, rate_hz=200.0,
+                                  nframes=args.serve_frames)
+        ctx.server_start(slots=4, max_batch_rays=1 << 24)
+        # warm-up: one request of each resolution
+        warm = [ctx.submit(fields[0], r.views, wl.step_adaptive) for r in reqs[:3]]
+        while any(ctx.poll(t) is None for t in warm):
+            time.sleep(0.001)
+        for t in warm:
+            ctx.request_release(t)
+        log(f"bench: serving {len(reqs)} requests over {args.serve_seconds:.1f} s on {len(fields)} resident frames")
+        outstanding, lat, rays_done = {}, [], 0
+        i = 0
+        t0 = time.perf_counter()
+        t_last = t0
+        while i < len(reqs) or outstanding:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i].t_arrive <= now:
+                r = reqs[i]
+                outstanding[ctx.submit(fields[r.frame], r.views, wl.step_adaptive)] = sum(v.nrays for v in r.views)
+                i += 1
+            for t in list(outstanding):
+                v = ctx.poll(t)
+                if v is not None:
+                    lat.append(v)
+                    rays_done += outstanding.pop(t)
+                    ctx.request_release(t)
+                    t_last = time.perf_counter()
+            if now > args.serve_seconds * 4 + 30:
+                raise RuntimeError("serving run did not drain")
+            time.sleep(0.0002)
+        ctx.server_stop()
+        lat_ms = np.array(lat) * 1e3
+        offered = sum(sum(v.nrays for v in r.views) for r in reqs) / args.serve_seconds
+        return {"requests": len(reqs), "frames_resident": len(fields), "field_dtype": "f16",
+                "rate_hz": 200.0, "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                                                 "p99": float(np.percentile(lat_ms, 99)),
+                                                 "max": float(lat_ms.max())},
+                "sustained_rays_per_s": rays_done / (t_last - t0), "offered_rays_per_s": offered,
+                "workload": "config5: 1,048,576 particles advected 60 frames, 256^3 F16 fields resident, "
+                            "1-5 views of 640x360/1280x720/1920x1080 per request"}
+    finally:
+        ctx.close()
+
+
 def cpu_baseline(wl, args) -> dict:
     """The FP64 oracle on the host cores: full splat + a bounded ray sample."""
     import oracle
@@ -116,6 +186,9 @@ def main(argv=None):
     ap.add_argument("--cpu-rays", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pairs", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving run (0: skip)")
+    ap.add_argument("--serve-frames", type=int, default=60)
+    ap.add_argument("--no-membench", action="store_true")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,6 +237,23 @@ def main(argv=None):
             f"ray-steps {steps_total}, rays in volume {hits}; kernels " +
             ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in kt.items()))
 
+    def step_on(stream, k):
+        with torch.cuda.stream(stream):
+            f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype=args.dtype, store_scale=scale)
+            ctx.trace_views(f, wl.views, st_a, out=out_pipe[k])
+            f.release()
+    out_pipe = [haze.alloc_outputs(wl.nrays), haze.alloc_outputs(wl.nrays)]
+    pipe_ms = pipelined(ctx, torch, step_on, args.steps, args.warmup)
+    log(f"bench: pipelined (two streams, splat of frame i+1 under trace of frame i): {pipe_ms:.3f} ms/frame")
+    achievable = None
+    if not args.no_membench:
+        fb = wl.grid.nvox * (16 if args.dtype == "f32" else 8)
+        achievable = {"hbm_read_GBps": ctx.membench(4 << 30, 5),
+                      "field_sized_read_GBps": ctx.membench(fb, 50),
+                      "field_bytes": fb}
+        log(f"bench: achievable read bandwidth: 4 GiB buffer {achievable['hbm_read_GBps']:.0f} GB/s, "
+            f"field-sized ({fb >> 20} MiB) {achievable['field_sized_read_GBps']:.0f} GB/s")
+
     A, U = res["adaptive"], res["uniform"]
     rays_s = nrays / (A["ms"] * 1e-3)
     # dominant kernel of the adaptive step
@@ -172,19 +262,23 @@ def main(argv=None):
     roofline = None
     march_ms = avg["march"]
     march_gbs = A["steps"] * BYTES_PER_STEP[args.dtype] / (march_ms * 1e-3) / 1e9
-    if dominant == "march":
-        roofline = {"kernel": "k_march", "bound": "hbm", "achieved": march_gbs, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": march_gbs / HBM_PEAK_GBS, "traffic": None,
-                    "per_unit": f"{BYTES_PER_STEP[args.dtype]} B per ray-step (8 corners x 4 channels)"}
+    march_roof = {"kernel": "k_march", "bound": "hbm", "achieved": march_gbs, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": march_gbs / HBM_PEAK_GBS, "traffic": None,
+                  "per_unit": f"{BYTES_PER_STEP[args.dtype]} B gathered per ray-step (8 corners x 4 channels)",
+                  "launch_ms": march_ms}
+    if achievable:
+        march_roof["achievable_GBps_field_sized"] = achievable["field_sized_read_GBps"]
+        march_roof["frac_of_achievable"] = march_gbs / achievable["field_sized_read_GBps"]
     pairs = None
+    splat_roof = None
     if not args.no_pairs:
         pairs = count_pairs(torch, parts, wl.grid, wl.h)
-    if dominant == "splat_gather" and pairs is not None:
-        flops = pairs * 25.0
-        tf = flops / (avg["splat_gather"] * 1e-3) / 1e12
-        roofline = {"kernel": "k_splat", "bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
-                    "frac": tf / 78.6, "traffic": None,
-                    "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h"}
+        tf = pairs * 25.0 / (avg["splat_gather"] * 1e-3) / 1e12
+        splat_roof = {"kernel": "k_splat", "bound": "alu", "achieved": tf, "peak": FP32_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": tf / FP32_PEAK_TFLOPS, "traffic": None,
+                      "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h",
+                      "launch_ms": avg["splat_gather"], "units_per_launch": pairs}
+    roofline = splat_roof if dominant == "splat_gather" else march_roof
 
     line = {
         "metric": METRIC,
@@ -217,11 +311,21 @@ def main(argv=None):
         "march_gather_GBps": march_gbs,
         "splat_pairs": pairs,
         "roofline": roofline,
+        "rooflines": {"k_splat": splat_roof, "k_march": march_roof},
+        "pipelined": {"ms_per_frame": pipe_ms, "rays_per_s": nrays / (pipe_ms * 1e-3),
+                      "note": "two streams: the splat of frame i+1 overlaps the trace of frame i"},
+        "achievable_bandwidth": achievable,
+        "serving": None,
         "cpu_baseline": None,
     }
     if pairs is not None:
         line["splat_pairs_per_s"] = pairs / (avg["splat_gather"] * 1e-3)
     ctx.close()
+    if args.serve_seconds > 0:
+        line["serving"] = serving_leg(haze, torch, W, args)
+        sv = line["serving"]
+        log(f"bench: serving p50 {sv['latency_ms']['p50']:.2f} ms, p99 {sv['latency_ms']['p99']:.2f} ms, "
+            f"sustained {sv['sustained_rays_per_s'] / 1e6:.0f} M rays/s (offered {sv['offered_rays_per_s'] / 1e6:.0f})")
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on the host (cpu_baseline)")
         line["cpu_baseline"] = cpu_baseline(wl, args)

@@ -113,6 +113,14 @@ hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);
 hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int32_t reset);
 
+/* Achievable read bandwidth (GB/s) of a device buffer of `bytes` read `reps`
+ * times by a plain streaming kernel: buffers far above the 256 MB MALL measure
+ * HBM, field-sized ones measure the caches that serve the tracer.  Allocates
+ * (and frees) the buffer against the budget; synchronises `hip_stream`.
+ * Errors: HZ_E_INVALID (bytes < 4096, reps outside [1, 10000]), HZ_E_BUDGET,
+ * HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_membench(hz_ctx *ctx, uint64_t bytes, int32_t reps, double *read_gbps, void *hip_stream);
+
 /* ---------------------------------------------------------------------- */
 /* Index field (paper Sec. 3.3.1, Eqs. 12-13)                             */
 /* ---------------------------------------------------------------------- */

@@ -63,7 +63,7 @@ class hz_trace_out(C.Structure):
 
 
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
-           "hz_profile_read", "hz_splat_index_field",
+           "hz_profile_read", "hz_membench", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
            "hz_server_stop"]
@@ -84,6 +84,8 @@ def lib():
         L.hz_last_error.argtypes, L.hz_last_error.restype = [], C.c_char_p
         L.hz_ctx_memory.argtypes, L.hz_ctx_memory.restype = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], S
         L.hz_ctx_tune.argtypes, L.hz_ctx_tune.restype = [P, C.c_char_p, C.c_int64], S
+        L.hz_membench.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(C.c_double), P]
+        L.hz_membench.restype = S
         L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
         L.hz_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.hz_profile_read.restype = S
@@ -234,6 +236,13 @@ class Context:
 
     def tune(self, key: str, value: int):
         _check(lib().hz_ctx_tune(C.c_void_p(self.handle), key.encode(), int(value)), "ctx_tune")
+
+    def membench(self, nbytes: int, reps: int = 10, stream=None) -> float:
+        """Achievable read GB/s of a buffer of `nbytes` (see hz_membench)."""
+        g = C.c_double()
+        _check(lib().hz_membench(C.c_void_p(self.handle), int(nbytes), int(reps), C.byref(g), _stream(stream)),
+               "membench")
+        return g.value
 
     def profile_enable(self, enable: bool = True):
         _check(lib().hz_profile_enable(C.c_void_p(self.handle), 1 if enable else 0), "profile_enable")

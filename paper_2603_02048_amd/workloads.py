@@ -297,3 +297,94 @@ def analytic_grid_gauss(grid: Grid, amp: float, centre: Sequence[float], sigma: 
     r2 = ((cx[None, None, :] - centre[0]) ** 2 + (cy[None, :, None] - centre[1]) ** 2
           + (cz[:, None, None] - centre[2]) ** 2)
     return amp * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+# ---------------------------------------------------------------------------
+# serving workload: an advected frame sequence and Poisson request arrivals
+# ---------------------------------------------------------------------------
+
+class CurlNoise:
+    """Seeded divergence-free velocity v(x) = curl A(x), A = sum_m a_m sin(k_m . x + phi_m).
+
+    curl(a sin(k.x + phi)) = cos(k.x + phi) (k x a), so
+    v(x) = sum_m cos(k_m . x + phi_m) (k_m x a_m), scaled to the requested RMS speed.
+    """
+
+    def __init__(self, rng: np.random.Generator, nmodes: int = 16, wavelength=(0.25, 1.0), rms: float = 0.2):
+        lam = rng.uniform(wavelength[0], wavelength[1], nmodes)
+        dirs = rng.standard_normal((nmodes, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        self.k = dirs * (2.0 * math.pi / lam)[:, None]
+        self.a = rng.standard_normal((nmodes, 3))
+        self.phi = rng.uniform(0.0, 2.0 * math.pi, nmodes)
+        self.ka = np.cross(self.k, self.a)
+        # mean of cos^2 is 1/2 over random positions: scale the modes to the RMS speed
+        ms = 0.5 * float(np.sum(self.ka ** 2))
+        self.ka *= rms / math.sqrt(ms)
+
+    def velocity(self, x: np.ndarray) -> np.ndarray:
+        ph = x @ self.k.T + self.phi          # (N, M)
+        return np.cos(ph) @ self.ka           # (N, 3)
+
+
+def advect_frames(particles: Particles, lo, hi, nframes: int = 60, dt: float = 1.0 / 30.0, rms: float = 0.2,
+                  seed: int = 0, device=None):
+    """Yield `nframes` particle sets: positions advected by seeded curl noise with
+    midpoint steps, wrapped periodically into the box; masses travel with the
+    particles.  With `device` (a torch device) the arithmetic runs in torch
+    float64 there and frames are yielded as numpy float32 as well."""
+    rng = np.random.default_rng(seed + 2)
+    field = CurlNoise(rng, rms=rms)
+    lo64 = np.asarray(lo, np.float64)
+    hi64 = np.asarray(hi, np.float64)
+    x0 = np.stack([particles.x, particles.y, particles.z], 1).astype(np.float64)
+    if device is None:
+        xp_cos, x, lo_, ext = np.cos, x0, lo64, hi64 - lo64
+        k, phi, ka = field.k, field.phi, field.ka
+        to_np = lambda a: a
+        mod = np.mod
+    else:
+        import torch
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)
+        xp_cos, x, lo_, ext = torch.cos, t(x0), t(lo64), t(hi64 - lo64)
+        k, phi, ka = t(field.k), t(field.phi), t(field.ka)
+        to_np = lambda a: a.cpu().numpy()
+        mod = torch.remainder
+    vel = lambda y: xp_cos(y @ k.T + phi) @ ka
+    for f in range(nframes):
+        if f > 0:
+            mid = x + 0.5 * dt * vel(x)
+            x = x + dt * vel(mid)
+            x = lo_ + mod(x - lo_, ext)
+        x32 = to_np(x).astype(np.float32)
+        yield Particles(x=np.ascontiguousarray(x32[:, 0]), y=np.ascontiguousarray(x32[:, 1]),
+                        z=np.ascontiguousarray(x32[:, 2]), m=particles.m)
+
+
+@dataclass
+class Request:
+    t_arrive: float          # seconds from the start of the run
+    frame: int
+    views: List[View]
+
+
+def serving_requests(lo, hi, duration_s: float, rate_hz: float = 200.0, nframes: int = 60, seed: int = 0,
+                     resolutions=((640, 360), (1280, 720), (1920, 1080)), radius=(2.5, 5.0),
+                     max_views: int = 5) -> List[Request]:
+    """Poisson arrivals; each request: a random frame, 1..max_views cameras evenly
+    spaced on a ring of random radius and phase, one random resolution."""
+    rng = np.random.default_rng(seed + 3)
+    t = 0.0
+    out = []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        frame = int(rng.integers(0, nframes))
+        nv = int(rng.integers(1, max_views + 1))
+        w, h = resolutions[int(rng.integers(0, len(resolutions)))]
+        rad = float(rng.uniform(radius[0], radius[1]))
+        ph = float(rng.uniform(0.0, 2.0 * math.pi))
+        views = [ring_view(lo, hi, ph + 2.0 * math.pi * k / nv, rad, w, h) for k in range(nv)]
+        out.append(Request(t_arrive=t, frame=frame, views=views))
+    return out
