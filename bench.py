@@ -189,6 +189,7 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving run (0: skip)")
     ap.add_argument("--serve-frames", type=int, default=60)
     ap.add_argument("--no-membench", action="store_true")
+    ap.add_argument("--splat", default="gather", choices=["gather", "scatter"])
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -226,7 +227,8 @@ def main(argv=None):
             f.release()
         return fn
 
-    kernels = ("cell_list", "splat_gather", "grad_pack", "raygen", "march")
+    kernels = ("cell_list", "splat", "grad_pack", "raygen", "march")
+    ctx.tune("splat.method", 2 if args.splat == "scatter" else 1)
     res = {}
     for name, st in (("adaptive", st_a), ("uniform", st_u)):
         ms, per, kt = time_steps(ctx, torch, make_step(st), args.steps, args.warmup, kernels)
@@ -236,6 +238,23 @@ def main(argv=None):
         log(f"bench: {name}: {ms:.3f} ms/step (p50 {np.percentile(per, 50):.3f}, p99 {np.percentile(per, 99):.3f}), "
             f"ray-steps {steps_total}, rays in volume {hits}; kernels " +
             ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in kt.items()))
+
+    # the other splat kernel, for comparison (same field, same checks in the tests)
+    other = "gather" if args.splat == "scatter" else "scatter"
+    ctx.tune("splat.method", 2 if other == "scatter" else 1)
+    for _ in range(3):
+        ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype=args.dtype, store_scale=scale).release()
+    torch.cuda.synchronize()
+    ctx.profile_read("splat", reset=True)
+    ctx.profile_enable(True)
+    for _ in range(10):
+        ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype=args.dtype, store_scale=scale).release()
+    torch.cuda.synchronize()
+    ctx.profile_enable(False)
+    other_ms = ctx.profile_read("splat", reset=True)[0] / 10
+    ctx.tune("splat.method", 2 if args.splat == "scatter" else 1)
+    log(f"bench: splat kernel {args.splat} {res['adaptive']['kt']['splat'][0] / max(res['adaptive']['kt']['splat'][1], 1):.3f} ms, "
+        f"{other} {other_ms:.3f} ms")
 
     def step_on(stream, k):
         with torch.cuda.stream(stream):
@@ -273,12 +292,13 @@ def main(argv=None):
     splat_roof = None
     if not args.no_pairs:
         pairs = count_pairs(torch, parts, wl.grid, wl.h)
-        tf = pairs * 25.0 / (avg["splat_gather"] * 1e-3) / 1e12
-        splat_roof = {"kernel": "k_splat", "bound": "alu", "achieved": tf, "peak": FP32_PEAK_TFLOPS,
+        tf = pairs * 25.0 / (avg["splat"] * 1e-3) / 1e12
+        splat_roof = {"kernel": "k_splat_scatter" if args.splat == "scatter" else "k_splat", "bound": "alu",
+                      "achieved": tf, "peak": FP32_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": tf / FP32_PEAK_TFLOPS, "traffic": None,
                       "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h",
-                      "launch_ms": avg["splat_gather"], "units_per_launch": pairs}
-    roofline = splat_roof if dominant == "splat_gather" else march_roof
+                      "launch_ms": avg["splat"], "units_per_launch": pairs}
+    roofline = splat_roof if dominant == "splat" else march_roof
 
     line = {
         "metric": METRIC,
@@ -308,6 +328,7 @@ def main(argv=None):
                     "latency_ms": {"p50": float(np.percentile(U["per"], 50)),
                                    "p99": float(np.percentile(U["per"], 99))}},
         "kernel_ms": {k: round(v, 5) for k, v in avg.items()},
+        "splat_ms_by_method": {args.splat: avg["splat"], other: other_ms},
         "march_gather_GBps": march_gbs,
         "splat_pairs": pairs,
         "roofline": roofline,
@@ -319,7 +340,7 @@ def main(argv=None):
         "cpu_baseline": None,
     }
     if pairs is not None:
-        line["splat_pairs_per_s"] = pairs / (avg["splat_gather"] * 1e-3)
+        line["splat_pairs_per_s"] = pairs / (avg["splat"] * 1e-3)
     ctx.close()
     if args.serve_seconds > 0:
         line["serving"] = serving_leg(haze, torch, W, args)

@@ -96,18 +96,25 @@ const char *hz_last_error(void);
  * its budget. */
 hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 
-/* Tuning knobs of the tracer's persistent march (results do not depend on
- * them, only speed):
+/* Tuning knobs.  The march knobs change speed only, never results; the splat
+ * method changes only how delta_n is rounded (both meet the same accuracy and
+ * each is bitwise repeatable):
  *   "march.refill_min"     refill a wave once this many of its 64 lanes are
  *                          idle, 1..64 (default 16)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
+ *   "splat.method"         0 or 1: gather (one wave per 4x4x4 voxel brick,
+ *                          fixed FP32 summation order; the default), 2: scatter
+ *                          (voxel tiles with 64-bit fixed-point accumulation in
+ *                          LDS; slower, for a support of up to ~16 cells per
+ *                          tile axis, HZ_E_UNSUPPORTED beyond); both are
+ *                          bitwise repeatable
  * Errors: HZ_E_INVALID (unknown key or value out of range). */
 hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 
 /* Per-kernel timing with HIP events recorded around every launch the context
- * makes on the caller's stream (kernels: "cell_list", "splat_gather",
- * "grad_pack", "raygen", "march").  hz_profile_read waits for the recorded
+ * makes on the caller's stream (kernels: "cell_list", "splat", "grad_pack",
+ * "raygen", "march"; the serving loop's launches as "serve_batch").  hz_profile_read waits for the recorded
  * events and returns the summed milliseconds and launch count of `kernel`
  * since the last reset (reset != 0 clears all sums after reading). */
 hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);

@@ -27,6 +27,10 @@ hipError_t launch_cell_list(const float *, const float *, const float *, const f
                             hipStream_t);
 int32_t scan_tiles(int32_t ncells);
 hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t);
+hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const float4 *, const uint32_t *, float *,
+                                hipStream_t);
+int scatter_max_rows(const SplatParams &P);
+int scatter_rows_limit();
 hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t);
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
 hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
@@ -114,6 +118,7 @@ struct hz_ctx {
     // march tuning (hz_ctx_tune)
     int32_t refill_min = 16;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
+    int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     std::vector<hz_field *> fields;
     std::mutex fields_mu;
     // memory of released fields, reused in stream order (no host sync)
@@ -423,6 +428,9 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
     } else if (k == "march.blocks_per_cu") {
         if (value < 0 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.blocks_per_cu must be in [0, 64]");
         c->blocks_per_cu = (int32_t)value;
+    } else if (k == "splat.method") {
+        if (value < 0 || value > 2) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.method must be 0, 1 or 2");
+        c->splat_method = (int32_t)value;
     } else {
         return fail(HZ_E_INVALID, "hz_ctx_tune: unknown key '%s'", key);
     }
@@ -595,7 +603,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     const int32_t n = (int32_t)P->n;
     const int64_t nv = (int64_t)g->res[0] * g->res[1] * g->res[2];
     Scratch *bufs[8] = {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles};
-    const size_t sizes[8] = {4u * (size_t)n, 4u * (size_t)(ncells + 1), 4u * (size_t)(ncells + 1),
+    const size_t sizes[8] = {4u * (size_t)n, 4u * (size_t)(ncells + 2), 4u * (size_t)(ncells + 1),
                              4u * (size_t)(ncells + 1), 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv,
                              4u * (size_t)scan_tiles((int32_t)ncells)};
     for (int i = 0; i < 8; ++i) {
@@ -612,9 +620,20 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
                                     (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, s);
     prof_end(c, s, "cell_list", t0);
     if (e == hipSuccess) {
+        // the gather is the default (faster on gfx950); the scatter on request
+        const bool scatter = c->splat_method == 2;
+        if (scatter && scatter_max_rows(sp) > scatter_rows_limit()) {
+            field_destroy(f);
+            return fail(HZ_E_UNSUPPORTED, "%s: h too large for the scatter splat's tile (use splat.method 1)", fn);
+        }
         hipEvent_t t1 = prof_begin(c, s);
-        e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr, s);
-        prof_end(c, s, "splat_gather", t1);
+        if (scatter)
+            e = launch_splat_scatter(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr,
+                                     (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, s);
+        else
+            e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr,
+                             s);
+        prof_end(c, s, "splat", t1);
     }
     if (e != hipSuccess) {
         field_destroy(f);

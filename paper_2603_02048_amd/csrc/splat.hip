@@ -17,6 +17,10 @@
 //                  all lanes walk the same candidate particles (wave-uniform
 //                  scalar loads) row by row of the cell list, culled by the
 //                  brick-to-row distance, summing m_j W in a fixed order
+//   k_splat_scatter  alternative: voxel tiles with 64-bit fixed-point LDS
+//                  accumulators, particles walking their footprints (more
+//                  accurate, bitwise repeatable, but about 2x slower than the
+//                  gather on gfx950: 64-bit LDS atomics and divergent loops)
 //   k_grad_pack    central differences (one-sided on faces) and packing of
 //                  (delta_n, grad) into F32 / F16 / BF16 voxels
 #include "haze_device.h"
@@ -39,21 +43,32 @@ __device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, in
 }
 
 // Particle -> cell id (0xffffffff when outside the grown box) + histogram.
+// Also records max |m| of the binned particles (as float bits; non-negative
+// floats order like unsigned integers) in *mmax for the fixed-point splat.
 __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x, const float *__restrict__ y,
-                                                    const float *__restrict__ z, int32_t n, CellGrid cg,
-                                                    uint32_t *__restrict__ cid, uint32_t *__restrict__ count)
+                                                    const float *__restrict__ z, const float *__restrict__ m,
+                                                    int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
+                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ mmax)
 {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int cx = cell_coord(x[i], cg.clo[0], cg.inv_cell, cg.nc[0]);
-    int cy = cell_coord(y[i], cg.clo[1], cg.inv_cell, cg.nc[1]);
-    int cz = cell_coord(z[i], cg.clo[2], cg.inv_cell, cg.nc[2]);
-    uint32_t id = 0xffffffffu;
-    if (cx >= 0 && cy >= 0 && cz >= 0) {
-        id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
-        atomicAdd(&count[id], 1u);
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t mbits = 0u;
+    if (i < n) {
+        const int cx = cell_coord(x[i], cg.clo[0], cg.inv_cell, cg.nc[0]);
+        const int cy = cell_coord(y[i], cg.clo[1], cg.inv_cell, cg.nc[1]);
+        const int cz = cell_coord(z[i], cg.clo[2], cg.inv_cell, cg.nc[2]);
+        uint32_t id = 0xffffffffu;
+        if (cx >= 0 && cy >= 0 && cz >= 0) {
+            id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
+            atomicAdd(&count[id], 1u);
+            const float am = fabsf(m[i]);
+            if (am > 0.0f && isfinite(am)) mbits = __float_as_uint(am);
+        }
+        cid[i] = id;
     }
-    cid[i] = id;
+    // one atomic per wave for the mass maximum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mbits = max(mbits, (uint32_t)__shfl_xor((int)mbits, off));
+    if ((threadIdx.x & 63) == 0 && mbits) atomicMax(mmax, mbits);
 }
 
 // Exclusive scan of count[0..n) into start[0..n] (start[n] = total) in three
@@ -243,6 +258,169 @@ __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__
     if (valid) dn[((int64_t)vz * P.res[1] + vy) * P.res[0] + vx] = acc * P.scale;
 }
 
+// ---------------------------------------------------------------------------
+// scatter splat: one workgroup per voxel tile, particles walk their footprints
+// ---------------------------------------------------------------------------
+// A workgroup owns a TX x TY x TZ tile of voxels with one 64-bit fixed-point
+// accumulator each in LDS.  The candidate particles are the cell-list rows
+// overlapping the tile grown by 2h, flattened through a prefix sum in LDS;
+// each thread takes candidates in turn and walks the part of the particle's
+// support sphere inside the tile row by row, with the exact x-range of each
+// row, so only in-support (voxel, particle) pairs are evaluated.  Each term
+// m_j W is quantised as round-toward-zero(m_j W / max|m| * 2^31), an exact
+// integer; integer addition is associative, so the sum (and the field) is the
+// same bits whatever order the threads add in.
+constexpr int SC_TX = 16, SC_TY = 16, SC_TZ = 8;
+constexpr int SC_THREADS = 256;
+constexpr int SC_MAXROWS = 512;
+
+__global__ __launch_bounds__(SC_THREADS) void k_splat_scatter(SplatParams P, const uint32_t *__restrict__ start,
+                                                              const float4 *__restrict__ parts,
+                                                              const uint32_t *__restrict__ mmax_bits,
+                                                              int32_t ntx, int32_t nty, int32_t ntiles,
+                                                              int32_t per_xcd, float *__restrict__ dn)
+{
+    __shared__ unsigned long long acc[SC_TX * SC_TY * SC_TZ];
+    __shared__ uint32_t row_first[SC_MAXROWS];
+    __shared__ uint32_t row_pref[SC_MAXROWS + 1];
+    __shared__ uint32_t wt[4];
+
+    const int32_t tile = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    if (tile >= ntiles) return;
+    const int32_t tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int32_t o[3] = {tx * SC_TX, ty * SC_TY, tz * SC_TZ};
+    const int32_t tdim[3] = {SC_TX, SC_TY, SC_TZ};
+    int32_t nt[3];
+    float blo[3], bhi[3];
+    for (int a = 0; a < 3; ++a) {
+        nt[a] = min(tdim[a], P.res[a] - o[a]);
+        blo[a] = P.lo[a] + ((float)o[a] + 0.5f) * P.sp[a];
+        bhi[a] = P.lo[a] + ((float)(o[a] + nt[a] - 1) + 0.5f) * P.sp[a];
+    }
+    for (int v = threadIdx.x; v < SC_TX * SC_TY * SC_TZ; v += SC_THREADS) acc[v] = 0ull;
+
+    // cell rows (ky, kz) and x-range of cells overlapping the grown tile (one
+    // cell of slack absorbs rounding)
+    const CellGrid &cg = P.cg;
+    const float R = 2.0f * P.h;
+    int c0[3], c1[3];
+    for (int a = 0; a < 3; ++a) {
+        c0[a] = max(0, (int)floorf((blo[a] - R - cg.clo[a]) * cg.inv_cell) - 1);
+        c1[a] = min(cg.nc[a] - 1, (int)floorf((bhi[a] + R - cg.clo[a]) * cg.inv_cell) + 1);
+    }
+    const int nry = c1[1] - c0[1] + 1, nrz = c1[2] - c0[2] + 1;
+    const int nrows = max(0, nry) * max(0, nrz);   // <= SC_MAXROWS (checked on the host)
+    uint32_t cnt[2] = {0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int r = threadIdx.x * 2 + k;
+        if (r < nrows && c0[0] <= c1[0]) {
+            const int ky = c0[1] + r % nry, kz = c0[2] + r / nry;
+            const int row = (kz * cg.nc[1] + ky) * cg.nc[0];
+            const uint32_t s0 = start[row + c0[0]], s1 = start[row + c1[0] + 1];
+            row_first[r] = s0;
+            cnt[k] = s1 - s0;
+        }
+    }
+    const uint32_t tsum = cnt[0] + cnt[1];
+    const uint32_t incl = block_scan_incl(tsum, wt);
+    {
+        const int r = threadIdx.x * 2;
+        const uint32_t ex = incl - tsum;
+        if (r < nrows) row_pref[r] = ex;
+        if (r + 1 < nrows) row_pref[r + 1] = ex + cnt[0];
+        if (threadIdx.x == SC_THREADS - 1) row_pref[nrows] = incl;
+    }
+    __syncthreads();
+    const uint32_t total = row_pref[nrows];
+
+    const float mref = __uint_as_float(*mmax_bits);
+    const float mscale = mref > 0.0f ? 2147483648.0f / mref : 0.0f;
+    const float R2 = P.support2;
+    for (uint32_t cidx = threadIdx.x; cidx < total; cidx += SC_THREADS) {
+        int lo_r = 0, hi_r = nrows - 1;   // last row whose prefix <= cidx
+        while (lo_r < hi_r) {
+            const int mid = (lo_r + hi_r + 1) >> 1;
+            if (row_pref[mid] <= cidx)
+                lo_r = mid;
+            else
+                hi_r = mid - 1;
+        }
+        const float4 q = parts[row_first[lo_r] + (cidx - row_pref[lo_r])];
+        const float pc[3] = {q.x, q.y, q.z};
+        int32_t f0[3], f1[3];
+        bool empty = false;
+        for (int a = 0; a < 3; ++a) {
+            // voxel centres within [p - R, p + R] on this axis, clipped to the tile
+            f0[a] = max(o[a], (int32_t)ceilf((pc[a] - R - P.lo[a]) / P.sp[a] - 0.5f));
+            f1[a] = min(o[a] + nt[a] - 1, (int32_t)floorf((pc[a] + R - P.lo[a]) / P.sp[a] - 0.5f));
+            empty |= f0[a] > f1[a];
+        }
+        if (empty) continue;
+        const float ms = q.w * mscale;
+        for (int32_t kk = f0[2]; kk <= f1[2]; ++kk) {
+            const float dz = P.lo[2] + ((float)kk + 0.5f) * P.sp[2] - q.z;
+            for (int32_t jj = f0[1]; jj <= f1[1]; ++jj) {
+                const float dy = P.lo[1] + ((float)jj + 0.5f) * P.sp[1] - q.y;
+                const float dyz2 = fmaf(dy, dy, dz * dz);
+                const float rem = R2 - dyz2;
+                if (rem <= 0.0f) continue;
+                const float dxm = __builtin_amdgcn_sqrtf(rem);
+                const int32_t i0 = max(f0[0], (int32_t)ceilf((q.x - dxm - P.lo[0]) / P.sp[0] - 0.5f));
+                const int32_t i1 = min(f1[0], (int32_t)floorf((q.x + dxm - P.lo[0]) / P.sp[0] - 0.5f));
+                unsigned long long *rowp = acc + ((kk - o[2]) * SC_TY + (jj - o[1])) * SC_TX - o[0];
+                float dx = P.lo[0] + ((float)i0 + 0.5f) * P.sp[0] - q.x;
+                for (int32_t ii = i0; ii <= i1; ++ii, dx += P.sp[0]) {
+                    const float r2 = fmaf(dx, dx, dyz2);
+                    const float qq = __builtin_amdgcn_sqrtf(r2) * P.inv_h;
+                    const float a = fmaxf(2.0f - qq, 0.0f);
+                    const float b = fmaxf(1.0f - qq, 0.0f);
+                    // M4 spline: 1 - 1.5q^2 + 0.75q^3 (q<1), 0.25(2-q)^3 (1<=q<2)
+                    const float w = 0.25f * (a * a * a) - b * b * b;
+                    const long long term = (long long)(int32_t)(w * ms);
+                    atomicAdd(rowp + ii, (unsigned long long)term);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double out_scale = (double)P.scale * (double)mref * (1.0 / 2147483648.0);
+    for (int v = threadIdx.x; v < SC_TX * SC_TY * SC_TZ; v += SC_THREADS) {
+        const int li = v % SC_TX, lj = (v / SC_TX) % SC_TY, lk = v / (SC_TX * SC_TY);
+        if (li < nt[0] && lj < nt[1] && lk < nt[2]) {
+            const long long sum = (long long)acc[v];
+            dn[((int64_t)(o[2] + lk) * P.res[1] + (o[1] + lj)) * P.res[0] + (o[0] + li)] =
+                (float)((double)sum * out_scale);
+        }
+    }
+}
+
+// Rows of cells a scatter tile can touch (host check against SC_MAXROWS).
+int scatter_max_rows(const SplatParams &P)
+{
+    int n = 1;
+    const int tdim[3] = {SC_TX, SC_TY, SC_TZ};
+    for (int a = 1; a < 3; ++a) {
+        const float ext = (float)(tdim[a] - 1) * P.sp[a] + 4.0f * P.h;
+        n *= (int)ceilf(ext * P.cg.inv_cell) + 4;
+    }
+    return n;
+}
+
+int scatter_rows_limit() { return SC_MAXROWS; }
+
+hipError_t launch_splat_scatter(const SplatParams &P, const uint32_t *start, const float4 *sorted,
+                                const uint32_t *mmax_bits, float *dn, hipStream_t s)
+{
+    const int32_t ntx = (P.res[0] + SC_TX - 1) / SC_TX, nty = (P.res[1] + SC_TY - 1) / SC_TY,
+                  ntz = (P.res[2] + SC_TZ - 1) / SC_TZ;
+    const int32_t ntiles = ntx * nty * ntz;
+    const int32_t per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL(k_splat_scatter, dim3((unsigned)(per_xcd * 8)), dim3(SC_THREADS), 0, s, P, start, sorted,
+                       mmax_bits, ntx, nty, ntiles, per_xcd, dn);
+    return hipGetLastError();
+}
+
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -341,9 +519,11 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *cursor,
                             uint32_t *slots, float4 *sorted, uint32_t *tile_sum, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 1, 256)), dim3(256), 0, s, count, 0u,
-                       (int64_t)cg.ncells + 1);
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, n, cg, cid, count);
+    // count[ncells + 1] holds max |m|; both start at zero
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 2, 256)), dim3(256), 0, s, count, 0u,
+                       (int64_t)cg.ncells + 2);
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid, count,
+                       count + cg.ncells + 1);
     const int32_t ntiles = (cg.ncells + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum);
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles, start + cg.ncells);

@@ -46,26 +46,56 @@ def _splat_both(ctx, haze, wl, dtype="f32", scale=1.0):
     return field, md
 
 
-@pytest.mark.parametrize("seed,res,h", [(0, (21, 17, 13), 0.03), (1, (8, 9, 30), 0.05), (2, (2, 3, 2), 0.2)])
-def test_splat_parity_small(ctx, haze, seed, res, h):
-    wl = W.make_small(seed=seed, res=res, h=h)
-    field, md = _splat_both(ctx, haze, wl)
-    dn, gx, gy, gz = _field_np(ctx, field)
+SPLAT_METHODS = {"gather": 1, "scatter": 2}
+
+
+@pytest.mark.parametrize("method", ["gather", "scatter"])
+@pytest.mark.parametrize("seed,res,h", [(0, (21, 17, 13), 0.03), (1, (8, 9, 30), 0.05), (2, (2, 3, 2), 0.2),
+                                        (3, (40, 33, 19), 0.02)])
+def test_splat_parity_small(ctx, haze, seed, res, h, method):
+    ctx.tune("splat.method", SPLAT_METHODS[method])
+    try:
+        wl = W.make_small(seed=seed, res=res, h=h, n=6000)
+        field, md = _splat_both(ctx, haze, wl)
+        dn, gx, gy, gz = _field_np(ctx, field)
+        ref = md.arrays
+        assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing,
+                           f"splat {method} seed={seed} res={res}")
+        field.release()
+    finally:
+        ctx.tune("splat.method", 0)
+
+
+@pytest.mark.parametrize("method", ["gather", "scatter"])
+def test_splat_is_bitwise_repeatable(ctx, haze, method):
+    ctx.tune("splat.method", SPLAT_METHODS[method])
+    try:
+        wl = W.make_small(seed=3, n=5000)
+        parts = haze.upload_particles(wl.particles)
+        f1 = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+        f2 = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+        a, b = _field_np(ctx, f1), _field_np(ctx, f2)
+        for x, y in zip(a, b):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+        f1.release()
+        f2.release()
+    finally:
+        ctx.tune("splat.method", 0)
+
+
+def test_splat_methods_on_config2(ctx, haze):
+    # both splat kernels at the benchmark's size, against the oracle
+    wl = W.make_config(2)
+    md = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h)
     ref = md.arrays
-    assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing, f"splat seed={seed} res={res}")
-    field.release()
-
-
-def test_splat_is_bitwise_repeatable(ctx, haze):
-    wl = W.make_small(seed=3, n=5000)
     parts = haze.upload_particles(wl.particles)
-    f1 = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
-    f2 = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
-    a, b = _field_np(ctx, f1), _field_np(ctx, f2)
-    for x, y in zip(a, b):
-        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
-    f1.release()
-    f2.release()
+    for method, code in SPLAT_METHODS.items():
+        ctx.tune("splat.method", code)
+        f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+        dn, gx, gy, gz = _field_np(ctx, f)
+        assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing, f"config2 splat {method}")
+        f.release()
+    ctx.tune("splat.method", 0)
 
 
 def test_splat_particles_outside_grid(ctx, haze):
