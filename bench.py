@@ -36,10 +36,33 @@ HBM_PEAK_GBS = 8000.0
 # them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_PEAK_TFLOPS = 78.6
 BYTES_PER_STEP = {"f32": 128, "f16": 64, "bf16": 64}   # 8 corners x 4 channels
+COUNTERS = os.path.join(ROOT, "profiles", "counters_config2_f32.json")
+KERNEL_SOURCE = {"k_splat": "paper_2603_02048_amd/csrc/splat.hip",
+                 "k_march": "paper_2603_02048_amd/csrc/trace.hip"}
 
 
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel: str, row: str, config: int, dtype: str):
+    """HBM/fabric bytes per launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when
+    the workload differs from the counted one or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    if config != 2 or dtype != "f32" or not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        c = json.load(f)
+    src = KERNEL_SOURCE[kernel]
+    with open(os.path.join(ROOT, src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != c["source_sha256"].get(src):
+            return None
+    k = c["kernels"][row]
+    return {"bytes": k["fetch_bytes"] + k["write_bytes"], "read_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "fetch_scale": c["calibration"]["fetch_scale"],
+            "write_scale": c["calibration"]["write_scale"], "source": "profiles/counters_config2_f32.md"}
 
 
 def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=()):
@@ -190,6 +213,8 @@ def main(argv=None):
     ap.add_argument("--serve-frames", type=int, default=60)
     ap.add_argument("--no-membench", action="store_true")
     ap.add_argument("--splat", default="gather", choices=["gather", "scatter"])
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -227,6 +252,14 @@ def main(argv=None):
             f.release()
         return fn
 
+    if args.calib_copy_mib > 0:
+        a = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {args.calib_copy_mib} MiB done")
+        del a, b
     kernels = ("cell_list", "splat", "grad_pack", "raygen", "march")
     ctx.tune("splat.method", 2 if args.splat == "scatter" else 1)
     res = {}
@@ -285,6 +318,10 @@ def main(argv=None):
                   "unit": "GB/s", "frac": march_gbs / HBM_PEAK_GBS, "traffic": None,
                   "per_unit": f"{BYTES_PER_STEP[args.dtype]} B gathered per ray-step (8 corners x 4 channels)",
                   "launch_ms": march_ms}
+    tr = measured_traffic("k_march", "k_march (adaptive)", args.config, args.dtype)
+    if tr is not None and args.theta is None:
+        march_roof["traffic"] = tr["bytes"]
+        march_roof["traffic_detail"] = tr
     if achievable:
         march_roof["achievable_GBps_field_sized"] = achievable["field_sized_read_GBps"]
         march_roof["frac_of_achievable"] = march_gbs / achievable["field_sized_read_GBps"]
@@ -298,6 +335,10 @@ def main(argv=None):
                       "unit": "TFLOP/s", "frac": tf / FP32_PEAK_TFLOPS, "traffic": None,
                       "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h",
                       "launch_ms": avg["splat"], "units_per_launch": pairs}
+        tr = measured_traffic("k_splat", "k_splat", args.config, args.dtype)
+        if tr is not None and args.splat == "gather":
+            splat_roof["traffic"] = tr["bytes"]
+            splat_roof["traffic_detail"] = tr
     roofline = splat_roof if dominant == "splat" else march_roof
 
     line = {
