@@ -15,6 +15,8 @@ What each function follows in the paper:
   sample         Sec. 3.3.1 (trilinear n and grad n along the ray)
   trace_views    Sec. 3.3.2-3.3.3, Eqs. 16-18, Fig. 1 caption (straight outside),
                  Sec. 3.3.2 last paragraph (image purely from bending)
+  trace_scene    the same with planar scene surfaces anywhere along the ray
+                 (the slanted and two-board scenes of Sec. 4.2)
   reference_views  the continuous ODE of Eq. 15 through the same medium
                  (step halving + Richardson extrapolation)
   trace_rays_rk4 classical RK4 on Eq. 15, a cross-check of the reference
@@ -94,6 +96,9 @@ def lib():
         L.ho_trace_views.restype = C.c_int
         L.ho_trace_views.argtypes = [C.POINTER(_Medium), C.POINTER(_View), C.c_int32, C.POINTER(_Step), P,
                                      C.c_int64, P, P, P, P, P]
+        L.ho_trace_scene.restype = C.c_int
+        L.ho_trace_scene.argtypes = [C.POINTER(_Medium), C.POINTER(_View), C.c_int32, P, C.c_int32,
+                                     C.POINTER(_Step), P, C.c_int64, P, P, P, P, P, P]
         L.ho_trace_rays.restype = C.c_int
         L.ho_trace_rays.argtypes = [C.POINTER(_Medium), C.POINTER(_Step), P, P, C.c_int64, P, P, P, P]
         L.ho_trace_rays_rk4.restype = C.c_int
@@ -271,6 +276,25 @@ def trace_views(medium: Medium, views, step, ray_ids: Optional[np.ndarray] = Non
     rc = lib().ho_trace_views(medium.ref, _views(views), len(views), C.byref(_step(step)),
                               None if ids is None else _ptr(ids), n, _ptr(out["disp"]), _ptr(out["exit_pos"]),
                               _ptr(out["exit_dir"]), _ptr(out["steps"]), _ptr(out["status"]))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc}): ray id out of range")
+    return out
+
+
+def trace_scene(medium: Medium, views, quads, step, ray_ids: Optional[np.ndarray] = None) -> dict:
+    """trace_views with scene quads: `quads` is (K, 3, 3) = K x (origin, edge_u,
+    edge_v), each the parallelogram origin + u edge_u + v edge_v, 0 <= u, v <= 1.
+    Adds `surface` per ray: 0 backdrop plane, k + 1 quad k, 255 none."""
+    q = np.ascontiguousarray(np.asarray(quads, np.float64).reshape(-1, 3, 3))
+    total = sum(int(v.width) * int(v.height) for v in views)
+    ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, np.int64)
+    n = total if ids is None else int(ids.shape[0])
+    out = dict(disp=np.empty((n, 2)), exit_pos=np.empty((n, 3)), exit_dir=np.empty((n, 3)),
+               steps=np.empty(n, np.int64), status=np.empty(n, np.uint8), surface=np.empty(n, np.uint8))
+    rc = lib().ho_trace_scene(medium.ref, _views(views), len(views), _ptr(q) if q.shape[0] else None, q.shape[0],
+                              C.byref(_step(step)), None if ids is None else _ptr(ids), n, _ptr(out["disp"]),
+                              _ptr(out["exit_pos"]), _ptr(out["exit_dir"]), _ptr(out["steps"]),
+                              _ptr(out["status"]), _ptr(out["surface"]))
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc}): ray id out of range")
     return out

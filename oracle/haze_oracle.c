@@ -16,6 +16,9 @@
  *   - straight rays outside the volume              (Fig. 1 caption)
  *   - image formed only by bending, via intersecting the refracted ray with
  *     the scene                                     (Sec. 3.3.2, last paragraph)
+ *   - scene surfaces (planar parallelograms) met anywhere along the ray: before
+ *     the volume, on the chord of any step inside it, or after it; the first
+ *     one met ends the ray                          (Sec. 3.3.2; Sec. 4.2)
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes):
@@ -79,6 +82,12 @@ typedef struct {
     int64_t max_steps;
     double tau_term;
 } ho_step;
+
+/* A scene surface: the parallelogram o + u ea + v eb, 0 <= u, v <= 1, seen
+ * from either side. */
+typedef struct {
+    double o[3], ea[3], eb[3];
+} ho_quad;
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                               */
@@ -364,6 +373,72 @@ static int inside(const double lo[3], const double hi[3], const double c[3])
     return 1;
 }
 
+/* Is the point h, on the plane of q, inside the parallelogram?  Solves
+ * h - o = u ea + v eb + s (ea x eb) by Cramer's rule. */
+static int in_quad(const ho_quad *q, const double h[3])
+{
+    double nrm[3], r[3] = {h[0] - q->o[0], h[1] - q->o[1], h[2] - q->o[2]}, c[3];
+    cross3(q->ea, q->eb, nrm);
+    double det = dot3(nrm, nrm); /* det[ea eb nrm] = (ea x eb) . nrm */
+    cross3(r, q->eb, c);
+    double u = dot3(c, nrm) / det; /* det[r eb nrm] */
+    cross3(q->ea, r, c);
+    double v = dot3(c, nrm) / det; /* det[ea r nrm] */
+    return u >= 0.0 && u <= 1.0 && v >= 0.0 && v <= 1.0;
+}
+
+/* Signed distance-like value (h - o) . (ea x eb) of h from the plane of q. */
+static double quad_side(const ho_quad *q, const double h[3])
+{
+    double nrm[3], r[3] = {h[0] - q->o[0], h[1] - q->o[1], h[2] - q->o[2]};
+    cross3(q->ea, q->eb, nrm);
+    return dot3(r, nrm);
+}
+
+/* First quad met by the straight ray o + t d with t in [0, t_max]; returns its
+ * index (or -1) and the parameter t.  Ties go to the lower index. */
+static int cast_quads(const ho_quad *quads, int32_t nq, const double o[3], const double d[3], double t_max,
+                      double *t_hit)
+{
+    int best = -1;
+    double bt = t_max;
+    for (int32_t k = 0; k < nq; ++k) {
+        double nrm[3];
+        cross3(quads[k].ea, quads[k].eb, nrm);
+        double dn = dot3(d, nrm);
+        if (dn == 0.0) continue;
+        double t = -quad_side(&quads[k], o) / dn;
+        if (!(t >= 0.0) || t > bt || (t == bt && best >= 0)) continue;
+        double h[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+        if (!in_quad(&quads[k], h)) continue;
+        best = k;
+        bt = t;
+    }
+    *t_hit = bt;
+    return best;
+}
+
+/* First quad crossed by the chord a -> b of one step: the side value changes
+ * sign, or is zero at b, after being non-zero at a.  Returns its index (or -1)
+ * and the fraction lam in (0, 1] along the chord. */
+static int chord_quads(const ho_quad *quads, int32_t nq, const double a[3], const double b[3], double *lam_hit)
+{
+    int best = -1;
+    double bl = 2.0;
+    for (int32_t k = 0; k < nq; ++k) {
+        double sa = quad_side(&quads[k], a), sb = quad_side(&quads[k], b);
+        if (sa == 0.0 || (sa > 0.0 && sb > 0.0) || (sa < 0.0 && sb < 0.0)) continue;
+        double lam = sa / (sa - sb);
+        if (!(lam < bl)) continue;
+        double h[3] = {a[0] + lam * (b[0] - a[0]), a[1] + lam * (b[1] - a[1]), a[2] + lam * (b[2] - a[2])};
+        if (!in_quad(&quads[k], h)) continue;
+        best = k;
+        bl = lam;
+    }
+    *lam_hit = bl;
+    return best;
+}
+
 /* ------------------------------------------------------------------ */
 /* step control (Sec. 3.3.3, Eqs. 17-18) and the march (Eq. 16)       */
 /* ------------------------------------------------------------------ */
@@ -410,19 +485,38 @@ double ho_advance(const ho_medium *md, const ho_step *st, double te, double c[3]
 
 /* March one ray from o along unit d.  The ray is straight until it meets the
  * box; inside, Eq. 16 is applied with the step of Eq. 18 (or the fixed step).
- * Returns the status; x_out / w_out get the last position and direction. */
-static int march(const ho_medium *md, const ho_step *st, const double o[3], const double d[3],
-                 double x_out[3], double w_out[3], int64_t *steps_out)
+ * Returns the status; x_out / w_out get the last position and direction.
+ *
+ * With scene quads (nq > 0): a quad met by the straight ray before the box
+ * ends the ray there (x_out = o, no steps); inside the box each step's chord
+ * C_k -> C_{k+1} is tested and the first quad crossed ends the ray at the
+ * crossing point (x_out = that point, w_out = omega_{k+1}).  *surf_out gets
+ * the quad index and hit_out the point, or -1 when no quad was met on the way
+ * (the caller then casts the straight exit ray). */
+static int march(const ho_medium *md, const ho_step *st, const ho_quad *quads, int32_t nq, const double o[3],
+                 const double d[3], double x_out[3], double w_out[3], int64_t *steps_out, double hit_out[3],
+                 int *surf_out)
 {
     const double *lo = md->grid.lo, *hi = md->grid.hi;
     double t_in, t_out;
     *steps_out = 0;
+    *surf_out = -1;
     memcpy(w_out, d, sizeof(double) * 3);
     if (!slab(lo, hi, o, d, &t_in, &t_out) || t_out <= 0.0) {
         memcpy(x_out, o, sizeof(double) * 3);
         return HO_OK;
     }
     double s0 = t_in > 0.0 ? t_in : 0.0;
+    if (nq > 0) {
+        double th;
+        int qh = cast_quads(quads, nq, o, d, s0, &th);
+        if (qh >= 0) {
+            memcpy(x_out, o, sizeof(double) * 3);
+            for (int a = 0; a < 3; ++a) hit_out[a] = o[a] + th * d[a];
+            *surf_out = qh;
+            return HO_OK;
+        }
+    }
     double c[3] = {o[0] + s0 * d[0], o[1] + s0 * d[1], o[2] + s0 * d[2]};
     double w[3] = {d[0], d[1], d[2]};
     int64_t k = 0;
@@ -430,11 +524,22 @@ static int march(const ho_medium *md, const ho_step *st, const double o[3], cons
     for (;;) {
         double te = exit_distance(lo, hi, c, w);
         if (te <= st->tau_term) break;
+        double cp[3] = {c[0], c[1], c[2]};
         double n = ho_advance(md, st, te, c, w);
         ++k;
         if (!finite3(c) || !finite3(w) || !isfinite(n)) {
             status = HO_NONFINITE;
             break;
+        }
+        if (nq > 0) {
+            double lam;
+            int qh = chord_quads(quads, nq, cp, c, &lam);
+            if (qh >= 0) {
+                for (int a = 0; a < 3; ++a) c[a] = cp[a] + lam * (c[a] - cp[a]);
+                memcpy(hit_out, c, sizeof(c));
+                *surf_out = qh;
+                break;
+            }
         }
         if (!inside(lo, hi, c)) break;
         if (k >= st->max_steps) {
@@ -538,17 +643,10 @@ static void pixel_ray(const cam_frame *cf, int64_t p, int64_t q, double d[3])
     normalize3(d);
 }
 
-/* Straight segment from the exit point to the backdrop plane, re-projected
- * through the same pinhole: displacement = projected point - pixel centre. */
-static int backdrop_disp(const cam_frame *cf, const ho_view *v, int64_t p, int64_t q, const double x[3],
-                         const double w[3], double disp[2])
+/* Re-projection of a scene point through the pinhole: displacement =
+ * projected point - centre of pixel (p, q). */
+static int project_disp(const cam_frame *cf, int64_t p, int64_t q, const double hit[3], double disp[2])
 {
-    double denom = dot3(w, v->plane_n);
-    if (!(denom < 0.0)) return HO_NOHIT;
-    double dp[3] = {v->plane_p[0] - x[0], v->plane_p[1] - x[1], v->plane_p[2] - x[2]};
-    double t = dot3(dp, v->plane_n) / denom;
-    if (t < 0.0) return HO_NOHIT;
-    double hit[3] = {x[0] + t * w[0], x[1] + t * w[1], x[2] + t * w[2]};
     double rel[3] = {hit[0] - cf->eye[0], hit[1] - cf->eye[1], hit[2] - cf->eye[2]};
     double xc = dot3(rel, cf->r), yc = dot3(rel, cf->u), zc = dot3(rel, cf->f);
     if (!(zc > 0.0)) return HO_NOHIT;
@@ -557,6 +655,28 @@ static int backdrop_disp(const cam_frame *cf, const ho_view *v, int64_t p, int64
     disp[0] = px - ((double)p + 0.5);
     disp[1] = py - ((double)q + 0.5);
     return HO_OK;
+}
+
+/* Parameter t >= 0 at which the straight ray x + t w meets the backdrop plane
+ * from its front side (w . N < 0), or -1. */
+static double backdrop_t(const ho_view *v, const double x[3], const double w[3])
+{
+    double denom = dot3(w, v->plane_n);
+    if (!(denom < 0.0)) return -1.0;
+    double dp[3] = {v->plane_p[0] - x[0], v->plane_p[1] - x[1], v->plane_p[2] - x[2]};
+    double t = dot3(dp, v->plane_n) / denom;
+    return t >= 0.0 ? t : -1.0;
+}
+
+/* Straight segment from the exit point to the backdrop plane, re-projected
+ * through the same pinhole. */
+static int backdrop_disp(const cam_frame *cf, const ho_view *v, int64_t p, int64_t q, const double x[3],
+                         const double w[3], double disp[2])
+{
+    double t = backdrop_t(v, x, w);
+    if (t < 0.0) return HO_NOHIT;
+    double hit[3] = {x[0] + t * w[0], x[1] + t * w[1], x[2] + t * w[2]};
+    return project_disp(cf, p, q, hit, disp);
 }
 
 /* Decode a global ray id (views concatenated, row-major pixels). */
@@ -578,10 +698,16 @@ static int decode_ray(const ho_view *views, int32_t nviews, int64_t id, int32_t 
 }
 
 /* Outputs, caller-owned: disp [n][2], exit_pos [n][3], exit_dir [n][3],
- * steps [n], status [n].  ray_ids may be NULL (then ray i is global id i). */
-int ho_trace_views(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_step *st,
-                   const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos, double *exit_dir,
-                   int64_t *steps, uint8_t *status)
+ * steps [n], status [n], surface [n] (may be NULL).  ray_ids may be NULL (then
+ * ray i is global id i).
+ *
+ * The image point of a ray is the first scene surface it meets: a quad met
+ * before or inside the volume ends the ray (see march); otherwise the straight
+ * exit ray is cast against the quads and the view's backdrop plane and the
+ * nearest wins (quads win ties).  surface: 0 backdrop, k + 1 quad k, 255 none. */
+int ho_trace_scene(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_quad *quads, int32_t nq,
+                   const ho_step *st, const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos,
+                   double *exit_dir, int64_t *steps, uint8_t *status, uint8_t *surface)
 {
     cam_frame *cfs = (cam_frame *)malloc(sizeof(cam_frame) * (size_t)(nviews > 0 ? nviews : 1));
     if (!cfs) return -1;
@@ -595,15 +721,32 @@ int ho_trace_views(const ho_medium *md, const ho_view *views, int32_t nviews, co
             bad = 1;
             continue;
         }
-        double d[3], x[3], w[3], dd[2] = {NAN, NAN};
+        double d[3], x[3], w[3], hit[3], dd[2] = {NAN, NAN};
         int64_t k;
+        int surf;
         pixel_ray(&cfs[vi], p, q, d);
-        int s = march(md, st, cfs[vi].eye, d, x, w, &k);
+        int s = march(md, st, quads, nq, cfs[vi].eye, d, x, w, &k, hit, &surf);
+        int sid = 255;
         if (s != HO_NONFINITE) {
-            int b = backdrop_disp(&cfs[vi], &views[vi], p, q, x, w, dd);
+            if (surf < 0) {
+                double tq, tb = backdrop_t(&views[vi], x, w);
+                int qh = nq > 0 ? cast_quads(quads, nq, x, w, INFINITY, &tq) : -1;
+                if (qh >= 0 && (tb < 0.0 || tq <= tb)) {
+                    surf = qh;
+                    for (int a = 0; a < 3; ++a) hit[a] = x[a] + tq * w[a];
+                } else if (tb >= 0.0) {
+                    surf = -2; /* backdrop */
+                    for (int a = 0; a < 3; ++a) hit[a] = x[a] + tb * w[a];
+                }
+            }
+            int b = surf == -1 ? HO_NOHIT : project_disp(&cfs[vi], p, q, hit, dd);
             if (b == HO_NOHIT && s == HO_OK) s = HO_NOHIT;
-            if (b == HO_NOHIT) dd[0] = dd[1] = NAN;
+            if (b == HO_NOHIT)
+                dd[0] = dd[1] = NAN;
+            else
+                sid = surf == -2 ? 0 : surf + 1;
         }
+        if (surface) surface[i] = (uint8_t)sid;
         disp[2 * i] = dd[0];
         disp[2 * i + 1] = dd[1];
         for (int a = 0; a < 3; ++a) {
@@ -617,6 +760,14 @@ int ho_trace_views(const ho_medium *md, const ho_view *views, int32_t nviews, co
     return bad ? -2 : 0;
 }
 
+int ho_trace_views(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_step *st,
+                   const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos, double *exit_dir,
+                   int64_t *steps, uint8_t *status)
+{
+    return ho_trace_scene(md, views, nviews, NULL, 0, st, ray_ids, nrays, disp, exit_pos, exit_dir, steps, status,
+                          NULL);
+}
+
 /* March explicit rays (origin, unit direction) without a camera. */
 int ho_trace_rays(const ho_medium *md, const ho_step *st, const double *origins, const double *dirs, int64_t nrays,
                   double *exit_pos, double *exit_dir, int64_t *steps, uint8_t *status)
@@ -625,7 +776,9 @@ int ho_trace_rays(const ho_medium *md, const ho_step *st, const double *origins,
     for (int64_t i = 0; i < nrays; ++i) {
         double x[3], w[3];
         int64_t k;
-        int s = march(md, st, origins + 3 * i, dirs + 3 * i, x, w, &k);
+        double hit[3];
+        int surf;
+        int s = march(md, st, NULL, 0, origins + 3 * i, dirs + 3 * i, x, w, &k, hit, &surf);
         for (int a = 0; a < 3; ++a) {
             exit_pos[3 * i + a] = x[a];
             exit_dir[3 * i + a] = w[a];
@@ -720,7 +873,9 @@ int ho_reference_views(const ho_medium *md, const ho_view *views, int32_t nviews
             int64_t k;
             st.ds_uniform = ds;
             st.max_steps = INT64_MAX;
-            march(md, &st, cfs[vi].eye, d, cur_x, cur_w, &k);
+            double hit[3];
+            int surf;
+            march(md, &st, NULL, 0, cfs[vi].eye, d, cur_x, cur_w, &k, hit, &surf);
             cur_d[0] = cur_d[1] = NAN;
             backdrop_disp(&cfs[vi], &views[vi], p, q, cur_x, cur_w, cur_d);
             if (have_prev) {

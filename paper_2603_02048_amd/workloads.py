@@ -171,6 +171,13 @@ def ring_view(lo, hi, azimuth: float, radius: float, width: int, height: int,
                 plane_p=_f32(plane_p), plane_n=_f32(-fwd))
 
 
+def quads(items) -> np.ndarray:
+    """Scene boards as a (K, 3, 3) float32 array of (origin, edge_u, edge_v):
+    each is the parallelogram origin + u edge_u + v edge_v, 0 <= u, v <= 1."""
+    a = np.asarray(items, np.float64).reshape(-1, 3, 3)
+    return a.astype(np.float32)
+
+
 def make_steps(grid: Grid, theta_max: float = 0.003, h_max_vox: float = 1.0,
                h_min_vox: float = 1.0 / 64.0, uniform_vox: float = 0.25,
                eps: float = 1e-12, max_steps: int = 1 << 20) -> tuple:
