@@ -258,6 +258,47 @@ hz_status hz_trace_views(hz_ctx *ctx, const hz_field *field, const hz_view *view
                          const hz_step *step, const int64_t *ray_ids, int64_t nrays, const hz_trace_out *out,
                          void *hip_stream);
 
+/* Scene boards (paper Sec. 3.3.2: the image is formed where the bent ray meets
+ * the scene; Sec. 4.2: boards at two depths, or one slanted board, viewed
+ * through the volume).  A board is the parallelogram
+ *     origin + u edge_u + v edge_v,  0 <= u, v <= 1,
+ * in metres, seen from either side. */
+#define HZ_MAX_QUADS 8
+typedef struct {
+    float origin[3];
+    float edge_u[3];
+    float edge_v[3];
+} hz_quad;
+
+/* Up to HZ_MAX_QUADS boards shared by all views of a call; host memory, read
+ * during the call only. */
+typedef struct {
+    int32_t nquads;
+    const hz_quad *quads;
+} hz_scene;
+
+/* hz_trace_views with scene boards.  A board can be met anywhere along a ray:
+ * before the volume (straight ray from the eye), inside it (the straight chord
+ * C_k -> C_{k+1} of each update step of Eq. 16 is tested, and the first board
+ * crossed ends the ray at the crossing point), or after it (the straight exit
+ * ray is cast against the boards and the view's backdrop plane, and the
+ * nearest wins; boards win ties).  Outputs as hz_trace_views, except:
+ *   exit_pos, exit_dir  for a ray that met a board inside the volume: the
+ *                       crossing point and the direction omega_{k+1} of that
+ *                       step; for a board met before the volume: the eye and
+ *                       the pixel direction (steps = 0)
+ *   disp                displacement of the board point the ray met
+ *   surface (device, uint8, one per output; may be NULL): 0 backdrop plane,
+ *                       k + 1 board k, 255 nothing met (HZ_RAY_NOHIT,
+ *                       HZ_RAY_NONFINITE, HZ_RAY_BAD_ID)
+ * `scene` may be NULL or hold 0 boards, which is hz_trace_views plus the
+ * surface output.  Errors: as hz_trace_views, and HZ_E_INVALID for nquads
+ * outside [0, HZ_MAX_QUADS], a NULL quads pointer with nquads > 0, non-finite
+ * board values or edges that are zero or parallel. */
+hz_status hz_trace_scene(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                         const hz_scene *scene, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                         const hz_trace_out *out, uint8_t *surface, void *hip_stream);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of multi-view requests                   */
 /* ---------------------------------------------------------------------- */

@@ -62,7 +62,7 @@ struct alignas(16) TraceJob {
     float *exit_dir;
     uint32_t *steps;
     uint8_t *status;
-    int64_t pad_;
+    uint8_t *surface;     // optional: 0 backdrop, k + 1 scene quad k, 255 none
 };
 
 struct TraceGrid {
@@ -88,6 +88,20 @@ struct TraceOutFlat {      // outputs indexed by queue position (ray-subset mode
     float *exit_dir;
     uint32_t *steps;
     uint8_t *status;
+    uint8_t *surface;
+};
+
+// A planar scene board (parallelogram), as affine functions of the position:
+//   side(x) = n . x - n0    (n unit normal; the board's plane is side = 0)
+//   u(x)    = du . x - du0,  v(x) = dv . x - dv0   (board = 0 <= u, v <= 1)
+// Up to kMaxQuads boards per launch, of which at most kMaxInner may come
+// within a voxel of the volume (those are tested on every step).
+constexpr int kMaxQuads = 8;
+constexpr int kMaxInner = 4;
+struct SceneQuad {
+    float n[3], n0;
+    float du[3], du0;
+    float dv[3], dv0;
 };
 
 struct TraceLaunch {
@@ -102,6 +116,10 @@ struct TraceLaunch {
     TraceGrid grid;
     TraceStep step;
     int32_t refill_min;    // refill a wave once this many lanes are idle
+    int32_t nquads;        // scene boards, tested before, inside and after the volume
+    int32_t ninner;        // boards that may cross the volume: tested on every step
+    uint32_t inner_idx;    // their indices, one byte each (lowest byte first)
+    const SceneQuad *quads;  // device copy of the nquads boards
 };
 
 // Field storage types (match hz_dtype).

@@ -35,7 +35,7 @@ hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3]
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
 hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t);
-int march_blocks_per_cu(int);
+int march_blocks_per_cu(int, int);
 }  // namespace haze
 
 using namespace haze;
@@ -114,7 +114,8 @@ struct hz_ctx {
     Scratch jobs, hits, counters;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
-    int march_bpc[3] = {0, 0, 0};
+    int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
+    int march_bpc_scene[2][3] = {};      // by board mode (outer / inner) and dtype
     // march tuning (hz_ctx_tune)
     int32_t refill_min = 16;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
@@ -257,7 +258,11 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
     c->num_cus = prop.multiProcessorCount;
     const uint64_t gib = 1ull << 30;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (free_b > gib ? free_b - gib : free_b / 2);
-    for (int d = 0; d < 3; ++d) c->march_bpc[d] = march_blocks_per_cu(d);
+    for (int d = 0; d < 3; ++d) {
+        c->march_bpc[d] = march_blocks_per_cu(d, 0);
+        c->march_bpc_scene[0][d] = march_blocks_per_cu(d, 1);
+        c->march_bpc_scene[1][d] = march_blocks_per_cu(d, 2);
+    }
     c->pinned.resize(8);
     *out = c;
     return HZ_OK;
@@ -845,11 +850,81 @@ static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes
     return HZ_OK;
 }
 
-extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
-                                    const hz_step *step, const int64_t *ray_ids, int64_t nrays,
-                                    const hz_trace_out *out, void *hip_stream)
+// Scene boards as affine side/u/v functions of the position (double on the
+// host, float for the kernels).  The inner boards are those whose bounding box
+// comes within one voxel of the volume, the only ones a step's chord can cross.
+static hz_status make_scene(const hz_scene *scene, const hz_grid &g, TraceLaunch *L, std::vector<SceneQuad> &qs,
+                            const char *fn)
 {
-    const char *fn = "hz_trace_views";
+    L->nquads = 0;
+    L->ninner = 0;
+    L->inner_idx = 0u;
+    qs.clear();
+    if (!scene || scene->nquads == 0) return HZ_OK;
+    if (scene->nquads < 0 || scene->nquads > kMaxQuads)
+        return fail(HZ_E_INVALID, "%s: nquads = %d outside [0, %d]", fn, scene->nquads, kMaxQuads);
+    if (!scene->quads) return fail(HZ_E_INVALID, "%s: NULL quads with nquads = %d", fn, scene->nquads);
+    double vox = INFINITY;
+    for (int a = 0; a < 3; ++a) vox = std::min(vox, (g.hi[a] - g.lo[a]) / g.res[a]);
+    qs.resize((size_t)scene->nquads);
+    for (int k = 0; k < scene->nquads; ++k) {
+        const hz_quad &q = scene->quads[k];
+        double o[3], ea[3], eb[3];
+        for (int a = 0; a < 3; ++a) {
+            o[a] = q.origin[a];
+            ea[a] = q.edge_u[a];
+            eb[a] = q.edge_v[a];
+            if (!std::isfinite(o[a]) || !std::isfinite(ea[a]) || !std::isfinite(eb[a]))
+                return fail(HZ_E_INVALID, "%s: board %d has non-finite values", fn, k);
+        }
+        const double x[3] = {ea[1] * eb[2] - ea[2] * eb[1], ea[2] * eb[0] - ea[0] * eb[2],
+                             ea[0] * eb[1] - ea[1] * eb[0]};
+        const double area = std::sqrt(dot3(x, x));
+        if (!(area > 1e-9 * std::sqrt(dot3(ea, ea) * dot3(eb, eb))) || !(area > 0.0))
+            return fail(HZ_E_INVALID, "%s: board %d has zero or parallel edges", fn, k);
+        const double n[3] = {x[0] / area, x[1] / area, x[2] / area};
+        // du = (eb x n) / area, dv = (n x ea) / area: u(o + u ea + v eb) = u, v(...) = v
+        const double du[3] = {(eb[1] * n[2] - eb[2] * n[1]) / area, (eb[2] * n[0] - eb[0] * n[2]) / area,
+                              (eb[0] * n[1] - eb[1] * n[0]) / area};
+        const double dv[3] = {(n[1] * ea[2] - n[2] * ea[1]) / area, (n[2] * ea[0] - n[0] * ea[2]) / area,
+                              (n[0] * ea[1] - n[1] * ea[0]) / area};
+        SceneQuad &Q = qs[(size_t)k];
+        for (int a = 0; a < 3; ++a) {
+            Q.n[a] = (float)n[a];
+            Q.du[a] = (float)du[a];
+            Q.dv[a] = (float)dv[a];
+        }
+        // offsets from the rounded coefficients, so side/u/v vanish at the origin
+        double on = 0.0, odu = 0.0, odv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            on += (double)Q.n[a] * o[a];
+            odu += (double)Q.du[a] * o[a];
+            odv += (double)Q.dv[a] * o[a];
+        }
+        Q.n0 = (float)on;
+        Q.du0 = (float)odu;
+        Q.dv0 = (float)odv;
+        bool overlap = true;
+        for (int a = 0; a < 3; ++a) {
+            const double c4[4] = {o[a], o[a] + ea[a], o[a] + eb[a], o[a] + ea[a] + eb[a]};
+            const double lo = *std::min_element(c4, c4 + 4), hi = *std::max_element(c4, c4 + 4);
+            if (hi < g.lo[a] - vox || lo > g.hi[a] + vox) overlap = false;
+        }
+        if (overlap) {
+            if (L->ninner == kMaxInner)
+                return fail(HZ_E_UNSUPPORTED, "%s: more than %d boards within a voxel of the volume", fn, kMaxInner);
+            L->inner_idx |= (uint32_t)k << (8 * L->ninner);
+            ++L->ninner;
+        }
+    }
+    L->nquads = scene->nquads;
+    return HZ_OK;
+}
+
+static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                            const hz_scene *scene, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                            const hz_trace_out *out, uint8_t *surface, void *hip_stream, const char *fn)
+{
     if (!c || !fc || !views || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
     hz_field *f = const_cast<hz_field *>(fc);
     if (f->ctx != c) return fail(HZ_E_INVALID, "%s: field belongs to another context", fn);
@@ -877,7 +952,7 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
     L.subset = subset ? 1 : 0;
     L.nslots = subset ? nrays : slot;
     L.ray_ids = ray_ids;
-    L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status};
+    L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status, surface};
     if (!subset)
         for (TraceJob &J : jobs) {
             const int64_t base = J.ray_begin;
@@ -886,7 +961,11 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
             J.exit_dir = out->exit_dir ? out->exit_dir + 3 * base : nullptr;
             J.steps = out->steps ? out->steps + base : nullptr;
             J.status = out->status ? out->status + base : nullptr;
+            J.surface = surface ? surface + base : nullptr;
         }
+    std::vector<SceneQuad> quads;
+    st = make_scene(scene, f->grid, &L, quads, fn);
+    if (st != HZ_OK) return st;
     make_trace_grid(f->grid, f->store_scale, &L.grid);
     make_trace_step(*step, f->grid, &L.step);
     L.refill_min = c->refill_min;
@@ -894,20 +973,28 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
 
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
+    // one upload: the view table, then the scene boards
     const size_t job_bytes = sizeof(TraceJob) * jobs.size();
-    st = scratch_acquire(c, c->jobs, job_bytes, s);
+    const size_t quad_bytes = sizeof(SceneQuad) * quads.size();
+    std::vector<unsigned char> table(job_bytes + quad_bytes);
+    std::memcpy(table.data(), jobs.data(), job_bytes);
+    if (quad_bytes) std::memcpy(table.data() + job_bytes, quads.data(), quad_bytes);
+    st = scratch_acquire(c, c->jobs, table.size(), s);
     if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->counters, 256, s);
     if (st != HZ_OK) return st;
-    st = staged_copy(c, c->jobs.ptr, jobs.data(), job_bytes, s);
+    st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s);
     if (st != HZ_OK) return st;
     L.jobs = (const TraceJob *)c->jobs.ptr;
+    L.quads = quad_bytes ? (const SceneQuad *)((unsigned char *)c->jobs.ptr + job_bytes) : nullptr;
     L.hits = (uint32_t *)c->hits.ptr;
     L.counters = (uint32_t *)c->counters.ptr;
     const int dt = (int)f->dtype;
     // persistent grid: what fits on the chip at once
     const int64_t want_blocks = (L.nslots + 255) / 256;
-    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, c->march_bpc[dt]) : c->march_bpc[dt];
+    const int fit = L.ninner > 0 ? c->march_bpc_scene[1][dt] : L.nquads > 0 ? c->march_bpc_scene[0][dt]
+                                                                            : c->march_bpc[dt];
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, fit) : fit;
     int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
     blocks64 = std::max<int64_t>(1, blocks64);
     const int blocks = (int)blocks64;
@@ -921,6 +1008,22 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
     scratch_release(c->hits, s);
     scratch_release(c->counters, s);
     return field_mark_used(f, s);
+}
+
+extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                                    const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                                    const hz_trace_out *out, void *hip_stream)
+{
+    return trace_impl(c, fc, views, nviews, nullptr, step, ray_ids, nrays, out, nullptr, hip_stream,
+                      "hz_trace_views");
+}
+
+extern "C" hz_status hz_trace_scene(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                                    const hz_scene *scene, const hz_step *step, const int64_t *ray_ids,
+                                    int64_t nrays, const hz_trace_out *out, uint8_t *surface, void *hip_stream)
+{
+    return trace_impl(c, fc, views, nviews, scene, step, ray_ids, nrays, out, surface, hip_stream,
+                      "hz_trace_scene");
 }
 
 // ---------------------------------------------------------------------------

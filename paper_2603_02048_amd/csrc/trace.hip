@@ -131,26 +131,89 @@ __device__ __forceinline__ float exit_distance(const TraceGrid &G, const float c
     return fmaxf(t, 0.0f);
 }
 
-// Exit ray -> backdrop plane -> re-projection -> displacement; writes outputs.
+__device__ __forceinline__ float quad_side(const SceneQuad &Q, const float x[3])
+{
+    return fmaf(Q.n[0], x[0], fmaf(Q.n[1], x[1], fmaf(Q.n[2], x[2], -Q.n0)));
+}
+
+__device__ __forceinline__ bool in_quad(const SceneQuad &Q, const float h[3])
+{
+    const float u = fmaf(Q.du[0], h[0], fmaf(Q.du[1], h[1], fmaf(Q.du[2], h[2], -Q.du0)));
+    const float v = fmaf(Q.dv[0], h[0], fmaf(Q.dv[1], h[1], fmaf(Q.dv[2], h[2], -Q.dv0)));
+    return u >= 0.0f && u <= 1.0f && v >= 0.0f && v <= 1.0f;
+}
+
+// First board met by the straight ray x + t w, t in [0, tmax]; ties go to the
+// lower index.  Returns the board index or -1, and t.
+__device__ __forceinline__ int cast_quads(const TraceLaunch &L, const float x[3], const float w[3], float tmax,
+                                          float &thit)
+{
+    int best = -1;
+    float bt = tmax;
+    for (int k = 0; k < L.nquads; ++k) {
+        const SceneQuad &Q = L.quads[k];
+        const float dn = Q.n[0] * w[0] + Q.n[1] * w[1] + Q.n[2] * w[2];
+        if (dn == 0.0f) continue;
+        const float t = -quad_side(Q, x) / dn;
+        if (!(t >= 0.0f) || t > bt || (t == bt && best >= 0)) continue;
+        const float h[3] = {fmaf(t, w[0], x[0]), fmaf(t, w[1], x[1]), fmaf(t, w[2], x[2])};
+        if (!in_quad(Q, h)) continue;
+        best = k;
+        bt = t;
+    }
+    thit = bt;
+    return best;
+}
+
+// Writes a finished ray.  With surf >= 0 the ray already met scene board surf
+// at hp; otherwise the straight ray (x, w) is cast against the boards and the
+// view's backdrop plane (front side only) and the nearest wins, boards on
+// ties.  The image point is re-projected through the pinhole: displacement =
+// projected point - pixel centre (Sec. 3.3.2).
+template <bool BOARDS>
 __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, const float x[3], const float w[3],
-                                           uint32_t steps, int status)
+                                           uint32_t steps, int status, const float *hp = nullptr, int surf = -1)
 {
     const TraceJob &J = L.jobs[r.job];
     float disp0 = __builtin_nanf(""), disp1 = __builtin_nanf("");
+    int sid = 255;
     if (status != 3) {
-        const float denom = w[0] * J.plane_n[0] + w[1] * J.plane_n[1] + w[2] * J.plane_n[2];
-        bool hit = denom < 0.0f;
-        float t = 0.0f;
+        float h[3];
+        bool hit = surf >= 0;
         if (hit) {
-            t = ((J.plane_p[0] - x[0]) * J.plane_n[0] + (J.plane_p[1] - x[1]) * J.plane_n[1] +
-                 (J.plane_p[2] - x[2]) * J.plane_n[2]) / denom;
-            hit = t >= 0.0f;
+            h[0] = hp[0]; h[1] = hp[1]; h[2] = hp[2];
+            sid = surf + 1;
+        } else {
+            const float denom = w[0] * J.plane_n[0] + w[1] * J.plane_n[1] + w[2] * J.plane_n[2];
+            float tb = -1.0f;
+            if (denom < 0.0f) {
+                tb = ((J.plane_p[0] - x[0]) * J.plane_n[0] + (J.plane_p[1] - x[1]) * J.plane_n[1] +
+                      (J.plane_p[2] - x[2]) * J.plane_n[2]) / denom;
+                if (!(tb >= 0.0f)) tb = -1.0f;
+            }
+            float t = tb;
+            hit = tb >= 0.0f;
+            sid = 0;
+            if (BOARDS) {
+                float tq;
+                const int q = cast_quads(L, x, w, hit ? tb : INFINITY, tq);
+                if (q >= 0) {
+                    t = tq;
+                    hit = true;
+                    sid = q + 1;
+                }
+            }
+            if (hit) {
+                h[0] = x[0] + t * w[0];
+                h[1] = x[1] + t * w[1];
+                h[2] = x[2] + t * w[2];
+            }
         }
         float zc = 0.0f, xc = 0.0f, yc = 0.0f;
         if (hit) {
-            const float hx = x[0] + t * w[0] - J.eye[0];
-            const float hy = x[1] + t * w[1] - J.eye[1];
-            const float hz = x[2] + t * w[2] - J.eye[2];
+            const float hx = h[0] - J.eye[0];
+            const float hy = h[1] - J.eye[1];
+            const float hz = h[2] - J.eye[2];
             xc = hx * J.r[0] + hy * J.r[1] + hz * J.r[2];
             yc = hx * J.u[0] + hy * J.u[1] + hz * J.u[2];
             zc = hx * J.f[0] + hy * J.f[1] + hz * J.f[2];
@@ -159,17 +222,22 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
         if (hit) {
             disp0 = (J.half_w + J.fpx * xc / zc) - ((float)r.p + 0.5f);
             disp1 = (J.half_h - J.fpx * yc / zc) - ((float)r.q + 0.5f);
-        } else if (status == 0) {
-            status = 2;
+        } else {
+            sid = 255;
+            if (status == 0) status = 2;
         }
     }
     float *disp, *ep, *ed;
     uint32_t *st;
-    uint8_t *stat;
+    uint8_t *stat, *sf;
     if (L.subset) {
         disp = L.flat.disp; ep = L.flat.exit_pos; ed = L.flat.exit_dir; st = L.flat.steps; stat = L.flat.status;
+        sf = L.flat.surface;
     } else {
-        disp = J.disp; ep = J.exit_pos; ed = J.exit_dir; st = J.steps; stat = J.status;
+        disp = J.disp; ep = J.exit_pos; ed = J.exit_dir; st = J.steps; stat = J.status; sf = J.surface;
+    }
+    if (BOARDS || sf) {
+        if (sf) sf[r.out] = (uint8_t)sid;
     }
     const int64_t o = r.out;
     if (disp) {
@@ -208,7 +276,21 @@ __global__ __launch_bounds__(256) void k_raygen(TraceLaunch L)
             const float d[3] = {d3.x, d3.y, d3.z};
             float t0;
             enters = enter_volume(L.grid, J.eye, d, t0);
-            if (!enters) finish_ray(L, r, J.eye, d, 0u, 0);
+            if (enters && L.nquads > 0) {
+                // a board in front of the volume ends the ray before it enters
+                float tq;
+                const int q = cast_quads(L, J.eye, d, t0, tq);
+                if (q >= 0) {
+                    const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
+                    finish_ray<true>(L, r, J.eye, d, 0u, 0, hp, q);
+                    enters = false;
+                }
+            } else if (!enters) {
+                if (L.nquads > 0)
+                    finish_ray<true>(L, r, J.eye, d, 0u, 0);
+                else
+                    finish_ray<false>(L, r, J.eye, d, 0u, 0);
+            }
         } else if (L.subset) {
             // ray id outside the views: flag it, leave no stale values behind
             const float nan = __builtin_nanf("");
@@ -219,6 +301,7 @@ __global__ __launch_bounds__(256) void k_raygen(TraceLaunch L)
                 L.flat.exit_dir[3 * slot] = L.flat.exit_dir[3 * slot + 1] = L.flat.exit_dir[3 * slot + 2] = nan;
             if (L.flat.steps) L.flat.steps[slot] = 0u;
             if (L.flat.status) L.flat.status[slot] = 4u;
+            if (L.flat.surface) L.flat.surface[slot] = 255u;
         }
     }
     // wave-aggregated append of the entering slots
@@ -355,7 +438,11 @@ __device__ __forceinline__ float face_distance(const TraceGrid &G, const float c
                  fminf(c[2] - G.lo[2], G.hi[2] - c[2]));
 }
 
-template <int DT>
+// SCENE 0: no scene boards; 1: boards, none near the volume (met only by the
+// straight exit ray); 2: some boards may cross the volume, so the chord of
+// every step is tested against those (L.ninner of them) and the first one
+// crossed ends the ray at the crossing point.
+template <int DT, int SCENE>
 __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 {
     const TraceGrid &G = L.grid;
@@ -386,6 +473,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
     float pnorm = 1.0f;
     float safe = 0.0f;   // lower bound of the distance from c to the box faces
     uint32_t steps = 0;
+    float side[SCENE == 2 ? kMaxInner : 1];   // side values of the inner boards at c
 
     for (;;) {
         const uint64_t idle = __ballot(!active);
@@ -431,6 +519,11 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                     safe = face_distance(G, c);
                     steps = 0;
                     active = true;
+                    if (SCENE == 2) {
+#pragma unroll
+                        for (int j = 0; j < kMaxInner; ++j)
+                            side[j] = j < L.ninner ? quad_side(L.quads[(L.inner_idx >> (8 * j)) & 255u], c) : 0.0f;
+                    }
                 }
             }
             next = min(next + nidle, end);
@@ -491,10 +584,38 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
             }
             ++steps;
             safe -= ds;
+            int surf = -1;
+            float hp[3];
+            if (SCENE == 2) {
+                // chord C_k -> C_{k+1} = C_{k+1} - ds w: the board whose side value
+                // changes sign (or reaches zero) first along it; ties go to the
+                // lower board index
+                float best = 2.0f;
+#pragma unroll
+                for (int j = 0; j < kMaxInner; ++j) {
+                    if (j >= L.ninner) continue;
+                    const int k = (int)((L.inner_idx >> (8 * j)) & 255u);
+                    const float s0 = side[j], s1 = quad_side(L.quads[k], c);
+                    side[j] = s1;
+                    if (s0 == 0.0f || (s0 > 0.0f && s1 > 0.0f) || (s0 < 0.0f && s1 < 0.0f)) continue;
+                    const float lam = s0 / (s0 - s1);
+                    if (!(lam < best)) continue;
+                    const float back = (1.0f - lam) * ds;
+                    const float h[3] = {fmaf(-back, w[0], c[0]), fmaf(-back, w[1], c[1]), fmaf(-back, w[2], c[2])};
+                    if (!in_quad(L.quads[k], h)) continue;
+                    best = lam;
+                    surf = k;
+                    hp[0] = h[0]; hp[1] = h[1]; hp[2] = h[2];
+                }
+            }
             // any inf or nan among position, direction and n makes the sum non-finite
             if (!isfinite(c[0] + c[1] + c[2] + w[0] + w[1] + w[2] + n))
                 status = 3;
-            else if (safe <= S.pos_eps &&
+            else if (SCENE == 2 && surf >= 0) {
+                finish_ray<true>(L, r, hp, w, steps, 0, hp, surf);
+                active = false;
+                continue;
+            } else if (safe <= S.pos_eps &&
                      (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] || c[2] < G.lo[2] ||
                       c[2] > G.hi[2]))
                 status = 0;
@@ -502,7 +623,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                 status = 1;
         }
         if (status >= 0) {
-            finish_ray(L, r, c, w, steps, status);
+            finish_ray<SCENE != 0>(L, r, c, w, steps, status);
             active = false;
         }
     }
@@ -520,27 +641,44 @@ hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s)
+template <int SCENE>
+static void launch_march_t(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s)
 {
     if (dtype == DT_F32)
-        hipLaunchKernelGGL(k_march<DT_F32>, dim3(march_blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_march<DT_F32, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
     else if (dtype == DT_F16)
-        hipLaunchKernelGGL(k_march<DT_F16>, dim3(march_blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_march<DT_F16, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
     else
-        hipLaunchKernelGGL(k_march<DT_BF16>, dim3(march_blocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_march<DT_BF16, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
+}
+
+hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s)
+{
+    if (L.ninner > 0)
+        launch_march_t<2>(dtype, L, march_blocks, s);
+    else if (L.nquads > 0)
+        launch_march_t<1>(dtype, L, march_blocks, s);
+    else
+        launch_march_t<0>(dtype, L, march_blocks, s);
     return hipGetLastError();
 }
 
-int march_blocks_per_cu(int dtype)
+int march_scene_mode(const TraceLaunch &L) { return L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0; }
+
+template <int SCENE>
+static hipError_t occupancy(int dtype, int *nb)
+{
+    if (dtype == DT_F32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_F32, SCENE>, 256, 0);
+    if (dtype == DT_F16) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_F16, SCENE>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_BF16, SCENE>, 256, 0);
+}
+
+int march_blocks_per_cu(int dtype, int scene_mode)
 {
     int nb = 0;
-    hipError_t e;
-    if (dtype == DT_F32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_march<DT_F32>, 256, 0);
-    else if (dtype == DT_F16)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_march<DT_F16>, 256, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_march<DT_BF16>, 256, 0);
+    const hipError_t e = scene_mode == 2   ? occupancy<2>(dtype, &nb)
+                         : scene_mode == 1 ? occupancy<1>(dtype, &nb)
+                                           : occupancy<0>(dtype, &nb);
     if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }

@@ -62,9 +62,21 @@ class hz_trace_out(C.Structure):
                 ("status", C.c_void_p)]
 
 
+MAX_QUADS = 8
+
+
+class hz_quad(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("edge_u", C.c_float * 3), ("edge_v", C.c_float * 3)]
+
+
+class hz_scene(C.Structure):
+    _fields_ = [("nquads", C.c_int32), ("quads", C.POINTER(hz_quad))]
+
+
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
            "hz_profile_read", "hz_membench", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
+           "hz_trace_scene",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
            "hz_server_stop"]
 
@@ -103,6 +115,9 @@ def lib():
         L.hz_trace_views.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), P, C.c_int64,
                                      C.POINTER(hz_trace_out), P]
         L.hz_trace_views.restype = S
+        L.hz_trace_scene.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_scene), C.POINTER(hz_step),
+                                     P, C.c_int64, C.POINTER(hz_trace_out), P, P]
+        L.hz_trace_scene.restype = S
         L.hz_server_start.argtypes, L.hz_server_start.restype = [P, C.c_int32, C.c_int64], S
         L.hz_submit.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), C.POINTER(C.c_uint64)]
         L.hz_submit.restype = S
@@ -298,6 +313,31 @@ class Context:
             assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
         _check(lib().hz_trace_views(C.c_void_p(self.handle), C.c_void_p(field.handle), vs, len(views),
                                     C.byref(st), _ptr(ray_ids), n, C.byref(o), _stream(stream)), "trace_views")
+        return out
+
+    def trace_scene(self, field: Field, views: Sequence, quads, step, ray_ids: Optional[torch.Tensor] = None,
+                    out: Optional[dict] = None, stream=None) -> dict:
+        """trace_views with scene boards: `quads` is (K, 3, 3) = K x (origin,
+        edge_u, edge_v).  The outputs gain `surface` (uint8: 0 backdrop, k + 1
+        board k, 255 none)."""
+        total = sum(int(v.width) * int(v.height) for v in views)
+        n = total if ray_ids is None else int(ray_ids.numel())
+        if out is None:
+            out = alloc_outputs(n)
+        if "surface" not in out:
+            out["surface"] = torch.empty(n, dtype=torch.uint8, device=out["status"].device)
+        o = hz_trace_out(_ptr(out.get("disp")), _ptr(out.get("exit_pos")), _ptr(out.get("exit_dir")),
+                         _ptr(out.get("steps")), _ptr(out.get("status")))
+        q = np.asarray(quads, np.float32).reshape(-1, 3, 3)
+        arr = (hz_quad * max(1, q.shape[0]))()
+        for k in range(q.shape[0]):
+            arr[k] = hz_quad((C.c_float * 3)(*q[k, 0]), (C.c_float * 3)(*q[k, 1]), (C.c_float * 3)(*q[k, 2]))
+        sc = hz_scene(q.shape[0], arr)
+        if ray_ids is not None:
+            assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
+        _check(lib().hz_trace_scene(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
+                                    len(views), C.byref(sc), C.byref(make_step(step)), _ptr(ray_ids), n,
+                                    C.byref(o), _ptr(out["surface"]), _stream(stream)), "trace_scene")
         return out
 
     # -- serving ----------------------------------------------------------
