@@ -310,6 +310,48 @@ def analytic_grid_gauss(grid: Grid, amp: float, centre: Sequence[float], sigma: 
 # serving workload: an advected frame sequence and Poisson request arrivals
 # ---------------------------------------------------------------------------
 
+def turbulence_field(grid: Grid, rms: float, outer: float, inner: float, seed: int = 0) -> np.ndarray:
+    """Statistically homogeneous, isotropic delta-n on the grid (array [z][y][x],
+    float64): a Gaussian random field with the von Karman spectrum
+        Phi(k) ~ (k^2 + (2 pi / outer)^2)^(-11/6) exp(-k^2 / (5.92 / inner)^2),
+    periodic over the box, scaled to the given RMS.  Input for the depth law
+    of the angle-of-arrival variance (Sec. 4.2, Eq. 19), which assumes
+    constant turbulence strength along the path."""
+    res = [int(r) for r in grid.res]
+    sp = grid.spacing
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((res[2], res[1], res[0]))
+    kz = 2 * np.pi * np.fft.fftfreq(res[2], sp[2])
+    ky = 2 * np.pi * np.fft.fftfreq(res[1], sp[1])
+    kx = 2 * np.pi * np.fft.rfftfreq(res[0], sp[0])
+    k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+    k0, km = 2 * np.pi / outer, 5.92 / inner
+    amp = np.sqrt((k2 + k0 * k0) ** (-11.0 / 6.0) * np.exp(-k2 / (km * km)))
+    f = np.fft.irfftn(np.fft.rfftn(white) * amp, s=white.shape, axes=(0, 1, 2))
+    f -= f.mean()
+    return f * (rms / f.std())
+
+
+def depth_views(lo, hi, n_side: int, width: int, height: int, vfov_deg: float, standoff: float = 0.01,
+                backdrop_beyond: float = 1.0) -> list:
+    """A square grid of n_side x n_side cameras just in front of the box's
+    y = lo face, all looking +y (up +z), spread over the face; the backdrop is
+    a plane of constant y beyond the box."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    views = []
+    for j in range(n_side):
+        for i in range(n_side):
+            ex = lo[0] + (i + 0.5) / n_side * (hi[0] - lo[0])
+            ez = lo[2] + (j + 0.5) / n_side * (hi[2] - lo[2])
+            eye = np.array([ex, lo[1] - standoff, ez])
+            views.append(View(eye=_f32(eye), fwd=_f32([0.0, 1.0, 0.0]), up=_f32([0.0, 0.0, 1.0]),
+                              vfov=float(np.float32(math.radians(vfov_deg))), width=int(width),
+                              height=int(height), plane_p=_f32([ex, hi[1] + backdrop_beyond, ez]),
+                              plane_n=_f32([0.0, -1.0, 0.0])))
+    return views
+
+
 class CurlNoise:
     """Seeded divergence-free velocity v(x) = curl A(x), A = sum_m a_m sin(k_m . x + phi_m).
 
