@@ -22,12 +22,15 @@ struct CellGrid {
     int32_t ncells;
 };
 
+// Gather-splat brick: 8 x 8 lanes in x-y, each lane a column of 4 voxels in z.
+constexpr int SPLAT_BX = 8, SPLAT_BY = 8, SPLAT_BZ = 4;
+
 // Geometry and constants of one splat launch.
 struct SplatParams {
     float lo[3];          // grid box corner
     float sp[3];          // voxel spacing
     int32_t res[3];
-    int32_t nbx, nby, nbz; // bricks of 4x4x4 voxels per axis
+    int32_t nbx, nby, nbz; // gather bricks (SPLAT_BX x SPLAT_BY x SPLAT_BZ voxels) per axis
     float h;
     float inv_h;
     float support2;       // (2h)^2
@@ -111,8 +114,9 @@ struct TraceLaunch {
     int64_t nslots;
     const int64_t *ray_ids;
     TraceOutFlat flat;
-    uint32_t *hits;        // compacted slots whose rays enter the volume
-    uint32_t *counters;    // [0] hit count, [1] head of the dynamic hit batches
+    uint32_t *hits;        // slots of the rays that enter the volume, in kHitSegs segments
+    uint32_t *counters;    // segment counts and the head of the dynamic batches (hit_counter)
+    uint32_t seg_cap;      // capacity of one hit segment (hit_seg_cap)
     TraceGrid grid;
     TraceStep step;
     int32_t refill_min;    // refill a wave once this many lanes are idle
@@ -121,6 +125,24 @@ struct TraceLaunch {
     uint32_t inner_idx;    // their indices, one byte each (lowest byte first)
     const SceneQuad *quads;  // device copy of the nquads boards
 };
+
+// Ray generation appends the entering rays to kHitSegs segments of the hit
+// list, workgroup b to segment b % kHitSegs (the workgroups of one XCD), with
+// one atomic per workgroup on that segment's counter.  Counters sit
+// kCounterStride words (256 B) apart so that no two share a cache line; the
+// one after the segment counts is the march's dynamic batch head.
+constexpr int kHitSegs = 8;
+constexpr int kCounterStride = 64;
+constexpr int kRaygenBlock = 256;
+constexpr size_t kCounterBytes = (size_t)(kHitSegs + 1) * kCounterStride * 4;
+__host__ __device__ inline uint32_t *hit_counter(uint32_t *counters, int k) { return counters + k * kCounterStride; }
+// Segment capacity: the slots of every workgroup that appends to one segment.
+inline uint32_t hit_seg_cap(int64_t nslots)
+{
+    const int64_t blocks = (nslots + kRaygenBlock - 1) / kRaygenBlock;
+    return (uint32_t)(((blocks + kHitSegs - 1) / kHitSegs) * kRaygenBlock);
+}
+inline size_t hit_list_bytes(int64_t nslots) { return 4u * (size_t)kHitSegs * hit_seg_cap(nslots); }
 
 // Field storage types (match hz_dtype).
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };

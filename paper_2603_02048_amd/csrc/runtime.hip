@@ -23,7 +23,7 @@
 
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
-                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, uint32_t *,
+                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, uint32_t *, bool,
                             hipStream_t);
 int32_t scan_tiles(int32_t ncells);
 hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t);
@@ -594,9 +594,9 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         sp.sp[a] = (float)((g->hi[a] - g->lo[a]) / g->res[a]);
         sp.res[a] = g->res[a];
     }
-    sp.nbx = (g->res[0] + 3) / 4;
-    sp.nby = (g->res[1] + 3) / 4;
-    sp.nbz = (g->res[2] + 3) / 4;
+    sp.nbx = (g->res[0] + SPLAT_BX - 1) / SPLAT_BX;
+    sp.nby = (g->res[1] + SPLAT_BY - 1) / SPLAT_BY;
+    sp.nbz = (g->res[2] + SPLAT_BZ - 1) / SPLAT_BZ;
     sp.h = prm->h;
     sp.inv_h = (float)(1.0 / h);
     sp.support2 = (float)(4.0 * h * h);
@@ -615,6 +615,10 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         st = scratch_acquire(c, *bufs[i], sizes[i], s);
         if (st != HZ_OK) return st;
     }
+    // the gather is the default (faster on gfx950); the scatter on request
+    const bool scatter = c->splat_method == 2;
+    if (scatter && scatter_max_rows(sp) > scatter_rows_limit())
+        return fail(HZ_E_UNSUPPORTED, "%s: h too large for the scatter splat's tile (use splat.method 1)", fn);
     hz_field *f = nullptr;
     st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
     if (st != HZ_OK) return st;
@@ -622,15 +626,9 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     hipEvent_t t0 = prof_begin(c, s);
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     (uint32_t *)c->start.ptr, (uint32_t *)c->cursor.ptr, (uint32_t *)c->slots.ptr,
-                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, s);
+                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s);
     prof_end(c, s, "cell_list", t0);
     if (e == hipSuccess) {
-        // the gather is the default (faster on gfx950); the scatter on request
-        const bool scatter = c->splat_method == 2;
-        if (scatter && scatter_max_rows(sp) > scatter_rows_limit()) {
-            field_destroy(f);
-            return fail(HZ_E_UNSUPPORTED, "%s: h too large for the scatter splat's tile (use splat.method 1)", fn);
-        }
         hipEvent_t t1 = prof_begin(c, s);
         if (scatter)
             e = launch_splat_scatter(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr,
@@ -980,8 +978,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     std::memcpy(table.data(), jobs.data(), job_bytes);
     if (quad_bytes) std::memcpy(table.data() + job_bytes, quads.data(), quad_bytes);
     st = scratch_acquire(c, c->jobs, table.size(), s);
-    if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
-    if (st == HZ_OK) st = scratch_acquire(c, c->counters, 256, s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->hits, hit_list_bytes(L.nslots), s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->counters, kCounterBytes, s);
     if (st != HZ_OK) return st;
     st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s);
     if (st != HZ_OK) return st;
@@ -989,6 +987,7 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     L.quads = quad_bytes ? (const SceneQuad *)((unsigned char *)c->jobs.ptr + job_bytes) : nullptr;
     L.hits = (uint32_t *)c->hits.ptr;
     L.counters = (uint32_t *)c->counters.ptr;
+    L.seg_cap = hit_seg_cap(L.nslots);
     const int dt = (int)f->dtype;
     // persistent grid: what fits on the chip at once
     const int64_t want_blocks = (L.nslots + 255) / 256;

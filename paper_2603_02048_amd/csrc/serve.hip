@@ -181,6 +181,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.ray_ids = nullptr;
     L.hits = (uint32_t *)sl.hits;
     L.counters = (uint32_t *)sl.counters;
+    L.seg_cap = hit_seg_cap(L.nslots);
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
     make_trace_step(head->step, field_grid(head->field), &L.step);
     L.refill_min = 16;
@@ -286,7 +287,7 @@ void server_destroy(Server *S)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.jobs) ctx_free(S->ctx, sl.jobs, sl.jobs_cap);
         if (sl.hits) ctx_free(S->ctx, sl.hits, sl.scratch_bytes);
-        if (sl.counters) ctx_free(S->ctx, sl.counters, 256);
+        if (sl.counters) ctx_free(S->ctx, sl.counters, kCounterBytes);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -315,9 +316,9 @@ extern "C" hz_status hz_server_start(hz_ctx *c, int32_t nslots, int64_t max_batc
     S->slot_capacity = (max_batch_rays + 63) / 64 * 64;
     S->slots.resize((size_t)nslots);
     for (Slot &sl : S->slots) {
-        sl.scratch_bytes = 4u * (size_t)S->slot_capacity;
+        sl.scratch_bytes = hit_list_bytes(S->slot_capacity);
         hz_status st = ctx_alloc(c, &sl.hits, sl.scratch_bytes);
-        if (st == HZ_OK) st = ctx_alloc(c, &sl.counters, 256);
+        if (st == HZ_OK) st = ctx_alloc(c, &sl.counters, kCounterBytes);
         if (st == HZ_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             st = set_error(HZ_E_DEVICE, "hz_server_start: hipStreamCreate failed");
         if (st == HZ_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)

@@ -13,10 +13,11 @@
 //   k_cell_scatter particle index -> a slot of its cell (arbitrary order)
 //   k_cell_order   per cell, rank the slots by particle index (stable order)
 //                  and gather (x, y, z, m) into cell-sorted float4 records
-//   k_splat        one wave per 4x4x4 voxel brick: every lane owns a voxel and
-//                  all lanes walk the same candidate particles (wave-uniform
-//                  scalar loads) row by row of the cell list, culled by the
-//                  brick-to-row distance, summing m_j W in a fixed order
+//   k_splat        one wave per 8x8x4 voxel brick: every lane owns a column of
+//                  4 voxels and all lanes walk the same candidate particles
+//                  (wave-uniform scalar loads) row by row of the cell list,
+//                  culled by the brick-to-row distance, summing m_j W in a
+//                  fixed order
 //   k_splat_scatter  alternative: voxel tiles with 64-bit fixed-point LDS
 //                  accumulators, particles walking their footprints (more
 //                  accurate, bitwise repeatable, but about 2x slower than the
@@ -43,8 +44,11 @@ __device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, in
 }
 
 // Particle -> cell id (0xffffffff when outside the grown box) + histogram.
-// Also records max |m| of the binned particles (as float bits; non-negative
-// floats order like unsigned integers) in *mmax for the fixed-point splat.
+// With MMAX, also records max |m| of the binned particles (as float bits;
+// non-negative floats order like unsigned integers) in *mmax for the
+// fixed-point splat: reduced over the workgroup first, so one atomic per
+// workgroup reaches the single address.
+template <bool MMAX>
 __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x, const float *__restrict__ y,
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
@@ -60,15 +64,24 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
         if (cx >= 0 && cy >= 0 && cz >= 0) {
             id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
             atomicAdd(&count[id], 1u);
-            const float am = fabsf(m[i]);
-            if (am > 0.0f && isfinite(am)) mbits = __float_as_uint(am);
+            if (MMAX) {
+                const float am = fabsf(m[i]);
+                if (am > 0.0f && isfinite(am)) mbits = __float_as_uint(am);
+            }
         }
         cid[i] = id;
     }
-    // one atomic per wave for the mass maximum
+    if (MMAX) {
+        __shared__ uint32_t wmax[4];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mbits = max(mbits, (uint32_t)__shfl_xor((int)mbits, off));
-    if ((threadIdx.x & 63) == 0 && mbits) atomicMax(mmax, mbits);
+        for (int off = 32; off > 0; off >>= 1) mbits = max(mbits, (uint32_t)__shfl_xor((int)mbits, off));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mbits;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t b = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+            if (b) atomicMax(mmax, b);
+        }
+    }
 }
 
 // Exclusive scan of count[0..n) into start[0..n] (start[n] = total) in three
@@ -183,10 +196,40 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
     }
 }
 
-// One wave per 4x4x4 brick, lane = voxel (lane & 3, (lane >> 2) & 3, lane >> 4).
-// Workgroups are remapped so that each XCD (workgroups are dealt round-robin
-// over the 8 XCDs) walks a contiguous run of bricks and keeps its particle
-// rows in its own L2.
+// Adds one candidate particle's M4-spline terms to the lane's column of voxels.
+__device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, float cy, const float *cz,
+                                                const float4 &q, float *acc)
+{
+    const float dx = cx - q.x, dy = cy - q.y;
+    const float dxy = fmaf(dx, dx, dy * dy);
+    if (dxy < P.support2) {
+#pragma unroll
+        for (int v = 0; v < SPLAT_BZ; ++v) {
+            const float dz = cz[v] - q.z;
+            const float r2 = fmaf(dz, dz, dxy);
+            if (r2 < P.support2) {
+                // M4 spline: 1 - 1.5q^2 + 0.75q^3 (q<1), 0.25(2-q)^3 (1<=q<2),
+                // written 0.25 a^3 - b^3 with a = 2 - q (> 0 here) and
+                // b = max(1 - q, 0)
+                const float a = fmaf(-__builtin_amdgcn_sqrtf(r2), P.inv_h, 2.0f);
+                const float b = fmaxf(a - 1.0f, 0.0f);
+                const float w = 0.25f * (a * a * a) - b * b * b;
+                acc[v] = fmaf(q.w, w, acc[v]);
+            }
+        }
+    }
+}
+
+// One wave per brick of 8 x 8 x 4 voxels: lane (lane & 7, lane >> 3) owns the
+// column of four voxels along z.  All lanes walk the same candidate particles
+// (the cell-list rows near the brick, with each row's x-range cut to the
+// support circle) through wave-uniform scalar loads; the x-y distance is
+// computed once per candidate and shared by the lane's four voxels, and a
+// candidate or voxel that no lane reaches is skipped wave-wide.  Every voxel
+// adds its terms in cell-row order, then particle index order, so the field
+// is bitwise repeatable.  Workgroups are remapped so that each XCD
+// (workgroups are dealt round-robin over the 8 XCDs) walks a contiguous run
+// of bricks and keeps its particle rows in its own L2.
 __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
                                                const float4 *__restrict__ parts, int32_t nbricks, int32_t per_xcd,
                                                float *__restrict__ dn)
@@ -199,18 +242,20 @@ __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__
     const int32_t bx = brick % P.nbx;
     const int32_t by = (brick / P.nbx) % P.nby;
     const int32_t bz = brick / (P.nbx * P.nby);
-    const int32_t vx = bx * 4 + (lane & 3), vy = by * 4 + ((lane >> 2) & 3), vz = bz * 4 + (lane >> 4);
-    const bool valid = vx < P.res[0] && vy < P.res[1] && vz < P.res[2];
+    const int32_t vx = bx * SPLAT_BX + (lane & 7), vy = by * SPLAT_BY + (lane >> 3), vz0 = bz * SPLAT_BZ;
     const float cx = P.lo[0] + ((float)vx + 0.5f) * P.sp[0];
     const float cy = P.lo[1] + ((float)vy + 0.5f) * P.sp[1];
-    const float cz = P.lo[2] + ((float)vz + 0.5f) * P.sp[2];
+    float cz[SPLAT_BZ];
+#pragma unroll
+    for (int v = 0; v < SPLAT_BZ; ++v) cz[v] = P.lo[2] + ((float)(vz0 + v) + 0.5f) * P.sp[2];
 
     // brick AABB of voxel centres (wave-uniform)
     float blo[3], bhi[3];
     {
-        const int32_t b0[3] = {bx * 4, by * 4, bz * 4};
+        const int32_t b0[3] = {bx * SPLAT_BX, by * SPLAT_BY, vz0};
+        const int32_t bd[3] = {SPLAT_BX, SPLAT_BY, SPLAT_BZ};
         for (int a = 0; a < 3; ++a) {
-            const int32_t i1 = min(b0[a] + 3, P.res[a] - 1);
+            const int32_t i1 = min(b0[a] + bd[a] - 1, P.res[a] - 1);
             blo[a] = P.lo[a] + ((float)b0[a] + 0.5f) * P.sp[a];
             bhi[a] = P.lo[a] + ((float)i1 + 0.5f) * P.sp[a];
         }
@@ -223,39 +268,43 @@ __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__
     const int cy0 = max(0, (int)floorf((blo[1] - R - cg.clo[1]) * cg.inv_cell) - 1);
     const int cy1 = min(cg.nc[1] - 1, (int)floorf((bhi[1] + R - cg.clo[1]) * cg.inv_cell) + 1);
 
-    float acc = 0.0f;
+    float acc[SPLAT_BZ];
+#pragma unroll
+    for (int v = 0; v < SPLAT_BZ; ++v) acc[v] = 0.0f;
     for (int kz = cz0; kz <= cz1; ++kz) {
         const float zl = cg.clo[2] + (float)kz * cg.cell;
         const float gz = fmaxf(0.0f, fmaxf(zl - bhi[2], blo[2] - (zl + cg.cell)));
         for (int ky = cy0; ky <= cy1; ++ky) {
             const float yl = cg.clo[1] + (float)ky * cg.cell;
             const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
-            // 1.0001 R^2 keeps the cull conservative under rounding
+            // 1.0001 R^2 keeps the cull conservative under rounding (and the
+            // 1-ulp hardware square root)
             const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
             if (rem <= 0.0f) continue;
-            const float dxm = sqrtf(rem);
+            const float dxm = __builtin_amdgcn_sqrtf(rem);
             const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
             const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
             if (kx0 > kx1) continue;
             const int row = (kz * cg.nc[1] + ky) * cg.nc[0];
             const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
             const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
-            for (uint32_t s = s0; s < s1; ++s) {
-                const float4 q = parts[s];
-                const float dx = cx - q.x, dy = cy - q.y, dz = cz - q.z;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                if (r2 < P.support2) {
-                    const float qq = __builtin_amdgcn_sqrtf(r2) * P.inv_h;
-                    const float a = fmaxf(2.0f - qq, 0.0f);
-                    const float b = fmaxf(1.0f - qq, 0.0f);
-                    // M4 spline: 1 - 1.5q^2 + 0.75q^3 (q<1), 0.25(2-q)^3 (1<=q<2)
-                    const float w = 0.25f * (a * a * a) - b * b * b;
-                    acc = fmaf(q.w, w, acc);
-                }
+            // two records per iteration: one wider scalar load and one wait
+            // for both, half the loop overhead; the terms are still added in
+            // index order
+            uint32_t s = s0;
+            for (; s + 1 < s1; s += 2) {
+                const float4 qa = parts[s], qb = parts[s + 1];
+                splat_candidate(P, cx, cy, cz, qa, acc);
+                splat_candidate(P, cx, cy, cz, qb, acc);
             }
+            if (s < s1) splat_candidate(P, cx, cy, cz, parts[s], acc);
         }
     }
-    if (valid) dn[((int64_t)vz * P.res[1] + vy) * P.res[0] + vx] = acc * P.scale;
+    if (vx < P.res[0] && vy < P.res[1]) {
+#pragma unroll
+        for (int v = 0; v < SPLAT_BZ; ++v)
+            if (vz0 + v < P.res[2]) dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = acc[v] * P.scale;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,13 +566,17 @@ int32_t scan_tiles(int32_t ncells) { return (ncells + SCAN_TILE - 1) / SCAN_TILE
 
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *cursor,
-                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, hipStream_t s)
+                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, bool want_mmax, hipStream_t s)
 {
-    // count[ncells + 1] holds max |m|; both start at zero
+    // count[ncells + 1] holds max |m| (scatter splat only); both start at zero
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 2, 256)), dim3(256), 0, s, count, 0u,
                        (int64_t)cg.ncells + 2);
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid, count,
-                       count + cg.ncells + 1);
+    if (want_mmax)
+        hipLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
+                           count, count + cg.ncells + 1);
+    else
+        hipLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
+                           count, count + cg.ncells + 1);
     const int32_t ntiles = (cg.ncells + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum);
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles, start + cg.ncells);

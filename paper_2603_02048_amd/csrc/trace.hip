@@ -258,13 +258,13 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
     if (stat) stat[o] = (uint8_t)status;
 }
 
-// counters[0]: hit count; counters[1]: head of the dynamic hit batches
+// Zero the segment counts and the dynamic batch head.
 __global__ void k_trace_init(uint32_t *counters)
 {
-    if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+    if (threadIdx.x <= kHitSegs) *hit_counter(counters, threadIdx.x) = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_raygen(TraceLaunch L)
+__global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool enters = false;
@@ -304,19 +304,44 @@ __global__ __launch_bounds__(256) void k_raygen(TraceLaunch L)
             if (L.flat.surface) L.flat.surface[slot] = 255u;
         }
     }
-    // wave-aggregated append of the entering slots
+    // workgroup-aggregated append of the entering slots to this workgroup's
+    // segment: wave ballots, wave offsets in LDS, one atomic per workgroup
+    __shared__ uint32_t wcount[kRaygenBlock / 64];
+    __shared__ uint32_t wbase;
     const uint64_t mask = __ballot(enters);
-    if (mask == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&L.counters[0], (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wcount[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w = 0; w < kRaygenBlock / 64; ++w) total += wcount[w];
+        wbase = total ? atomicAdd(hit_counter(L.counters, blockIdx.x % kHitSegs), total) : 0u;
+    }
+    __syncthreads();
     if (enters) {
+        uint32_t off = wbase;
+        for (int w = 0; w < wave; ++w) off += wcount[w];
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        L.hits[base + rank] = (uint32_t)slot;
+        L.hits[(size_t)(blockIdx.x % kHitSegs) * L.seg_cap + off + rank] = (uint32_t)slot;
     }
+}
+
+// Global hit index g -> slot, with the segments taken in order:
+// pre[k] = hits in segments before k (in LDS, read when a lane is refilled).
+__device__ __forceinline__ uint32_t hit_slot(const TraceLaunch &L, const uint32_t *pre, uint32_t g)
+{
+    int k = 0;
+    uint32_t base = 0;
+#pragma unroll
+    for (int j = 1; j < kHitSegs; ++j) {
+        const uint32_t p = pre[j];
+        if (g >= p) {
+            k = j;
+            base = p;
+        }
+    }
+    return L.hits[(size_t)k * L.seg_cap + (g - base)];
 }
 
 __device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
@@ -447,7 +472,17 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 {
     const TraceGrid &G = L.grid;
     const TraceStep &S = L.step;
-    const uint32_t nh = L.counters[0];
+    __shared__ uint32_t pre[kHitSegs + 1];
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kHitSegs; ++k) {
+            pre[k] = t;
+            t += *hit_counter(L.counters, k);
+        }
+        pre[kHitSegs] = t;
+    }
+    __syncthreads();
+    const uint32_t nh = __builtin_amdgcn_readfirstlane(pre[kHitSegs]);
     const uint32_t refill_min = (uint32_t)max(1, min(64, L.refill_min));
     const int lane = threadIdx.x & 63;
 
@@ -486,7 +521,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                     pending = false;
                 } else {
                     uint32_t v = 0;
-                    if (lane == 0) v = dyn0 + atomicAdd(&L.counters[1], 64u);
+                    if (lane == 0) v = dyn0 + atomicAdd(hit_counter(L.counters, kHitSegs), 64u);
                     b = __shfl(v, 0);
                 }
                 b = __builtin_amdgcn_readfirstlane(b);
@@ -501,7 +536,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                 const uint32_t k = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 if (k < end) {
-                    const int64_t slot = L.hits[k];
+                    const int64_t slot = hit_slot(L, pre, k);
                     decode_slot(L, slot, r);
                     const TraceJob &J = L.jobs[r.job];
                     field = J.field;
@@ -528,7 +563,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
             }
             next = min(next + nidle, end);
             if (next == end && !pending) {
-                if (lane == 0) pend_v = dyn0 + atomicAdd(&L.counters[1], 64u);
+                if (lane == 0) pend_v = dyn0 + atomicAdd(hit_counter(L.counters, kHitSegs), 64u);
                 pending = true;
             }
             continue;
@@ -637,7 +672,8 @@ hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s)
 {
     hipLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, L.counters);
     if (L.nslots > 0)
-        hipLaunchKernelGGL(k_raygen, dim3((unsigned)((L.nslots + 255) / 256)), dim3(256), 0, s, L);
+        hipLaunchKernelGGL(k_raygen, dim3((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock)),
+                           dim3(kRaygenBlock), 0, s, L);
     return hipGetLastError();
 }
 
