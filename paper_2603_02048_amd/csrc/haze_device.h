@@ -114,9 +114,10 @@ struct TraceLaunch {
     int64_t nslots;
     const int64_t *ray_ids;
     TraceOutFlat flat;
-    uint32_t *hits;        // slots of the rays that enter the volume, in kHitSegs segments
-    uint32_t *counters;    // segment counts and the head of the dynamic batches (hit_counter)
-    uint32_t seg_cap;      // capacity of one hit segment (hit_seg_cap)
+    uint32_t *hits;        // slots of the rays that enter the volume, sorted by length bin
+    uint8_t *slot_bin;     // per slot: length bin of an entering ray, 255 otherwise
+    uint32_t *counters;    // bin totals, placement cursors, march batch head (hit_counter)
+    float inv_len_bin;     // kRayBins / (box diagonal): chord length -> bin
     TraceGrid grid;
     TraceStep step;
     int32_t refill_min;    // refill a wave once this many lanes are idle
@@ -126,23 +127,21 @@ struct TraceLaunch {
     const SceneQuad *quads;  // device copy of the nquads boards
 };
 
-// Ray generation appends the entering rays to kHitSegs segments of the hit
-// list, workgroup b to segment b % kHitSegs (the workgroups of one XCD), with
-// one atomic per workgroup on that segment's counter.  Counters sit
-// kCounterStride words (256 B) apart so that no two share a cache line; the
-// one after the segment counts is the march's dynamic batch head.
-constexpr int kHitSegs = 8;
+// Ray generation sorts the entering rays by their straight chord through the
+// volume (a proxy for their step count), longest first, in kRayBins bins: the
+// march then hands out rays of similar length to each wave, so lanes finish
+// together, and the longest rays start first.  Pass 1 finishes the rays that
+// miss and counts the bins (one atomic per workgroup and non-empty bin); pass
+// 2 places each ray in its bin's range of the hit list.  Counters sit
+// kCounterStride words (256 B) apart so that no two share a cache line:
+// bin totals [0, kRayBins), placement cursors [kRayBins, 2 kRayBins), and the
+// march's dynamic batch head at 2 kRayBins.
+constexpr int kRayBins = 16;
 constexpr int kCounterStride = 64;
 constexpr int kRaygenBlock = 256;
-constexpr size_t kCounterBytes = (size_t)(kHitSegs + 1) * kCounterStride * 4;
+constexpr int kMarchHead = 2 * kRayBins;
+constexpr size_t kCounterBytes = (size_t)(kMarchHead + 1) * kCounterStride * 4;
 __host__ __device__ inline uint32_t *hit_counter(uint32_t *counters, int k) { return counters + k * kCounterStride; }
-// Segment capacity: the slots of every workgroup that appends to one segment.
-inline uint32_t hit_seg_cap(int64_t nslots)
-{
-    const int64_t blocks = (nslots + kRaygenBlock - 1) / kRaygenBlock;
-    return (uint32_t)(((blocks + kHitSegs - 1) / kHitSegs) * kRaygenBlock);
-}
-inline size_t hit_list_bytes(int64_t nslots) { return 4u * (size_t)kHitSegs * hit_seg_cap(nslots); }
 
 // Field storage types (match hz_dtype).
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };

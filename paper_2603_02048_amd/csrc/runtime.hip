@@ -111,7 +111,7 @@ struct hz_ctx {
     // splat scratch
     Scratch cid, count, start, cursor, slots, sorted, dn, tiles;
     // trace scratch
-    Scratch jobs, hits, counters;
+    Scratch jobs, hits, bins, counters;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
@@ -413,7 +413,7 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
         c->prof_free.clear();
     }
     for (Scratch *s : {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->jobs,
-                       &c->hits, &c->counters})
+                       &c->hits, &c->bins, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
         if (p.used && p.done) (void)hipEventSynchronize(p.done);
@@ -793,6 +793,14 @@ hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int6
     return HZ_OK;
 }
 
+// Chord length -> length bin of the ray sort: kRayBins bins over the box diagonal.
+float length_bin_scale(const hz_grid &g)
+{
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) d2 += (g.hi[a] - g.lo[a]) * (g.hi[a] - g.lo[a]);
+    return (float)(kRayBins / std::sqrt(d2));
+}
+
 void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G)
 {
     for (int a = 0; a < 3; ++a) {
@@ -978,7 +986,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     std::memcpy(table.data(), jobs.data(), job_bytes);
     if (quad_bytes) std::memcpy(table.data() + job_bytes, quads.data(), quad_bytes);
     st = scratch_acquire(c, c->jobs, table.size(), s);
-    if (st == HZ_OK) st = scratch_acquire(c, c->hits, hit_list_bytes(L.nslots), s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
+    if (st == HZ_OK) st = scratch_acquire(c, c->bins, (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->counters, kCounterBytes, s);
     if (st != HZ_OK) return st;
     st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s);
@@ -987,7 +996,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     L.quads = quad_bytes ? (const SceneQuad *)((unsigned char *)c->jobs.ptr + job_bytes) : nullptr;
     L.hits = (uint32_t *)c->hits.ptr;
     L.counters = (uint32_t *)c->counters.ptr;
-    L.seg_cap = hit_seg_cap(L.nslots);
+    L.slot_bin = (uint8_t *)c->bins.ptr;
+    L.inv_len_bin = length_bin_scale(f->grid);
     const int dt = (int)f->dtype;
     // persistent grid: what fits on the chip at once
     const int64_t want_blocks = (L.nslots + 255) / 256;
@@ -1005,6 +1015,7 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     prof_end(c, s, "march", t1);
     scratch_release(c->jobs, s);
     scratch_release(c->hits, s);
+    scratch_release(c->bins, s);
     scratch_release(c->counters, s);
     return field_mark_used(f, s);
 }

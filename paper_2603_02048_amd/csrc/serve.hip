@@ -33,6 +33,7 @@ hz_status check_step(const hz_step *st, const char *fn);
 hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
                    const char *fn, int index);
 void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G);
+float length_bin_scale(const hz_grid &g);
 void make_trace_step(const hz_step &st, const hz_grid &g, TraceStep *S);
 
 enum ReqState { REQ_PENDING = 0, REQ_RUNNING = 1, REQ_DONE = 2, REQ_FAILED = 3 };
@@ -61,6 +62,7 @@ struct Slot {
     void *pinned = nullptr;     // host staging of the job table
     size_t pinned_cap = 0;
     void *hits = nullptr;       // u32 per queue slot
+    void *bins = nullptr;       // u8 per queue slot (length bins of the ray sort)
     void *counters = nullptr;
     size_t scratch_bytes = 0;
 };
@@ -181,7 +183,8 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.ray_ids = nullptr;
     L.hits = (uint32_t *)sl.hits;
     L.counters = (uint32_t *)sl.counters;
-    L.seg_cap = hit_seg_cap(L.nslots);
+    L.slot_bin = (uint8_t *)sl.bins;
+    L.inv_len_bin = length_bin_scale(field_grid(head->field));
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
     make_trace_step(head->step, field_grid(head->field), &L.step);
     L.refill_min = 16;
@@ -287,6 +290,7 @@ void server_destroy(Server *S)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.jobs) ctx_free(S->ctx, sl.jobs, sl.jobs_cap);
         if (sl.hits) ctx_free(S->ctx, sl.hits, sl.scratch_bytes);
+        if (sl.bins) ctx_free(S->ctx, sl.bins, (size_t)S->slot_capacity);
         if (sl.counters) ctx_free(S->ctx, sl.counters, kCounterBytes);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         if (sl.done) (void)hipEventDestroy(sl.done);
@@ -316,8 +320,9 @@ extern "C" hz_status hz_server_start(hz_ctx *c, int32_t nslots, int64_t max_batc
     S->slot_capacity = (max_batch_rays + 63) / 64 * 64;
     S->slots.resize((size_t)nslots);
     for (Slot &sl : S->slots) {
-        sl.scratch_bytes = hit_list_bytes(S->slot_capacity);
+        sl.scratch_bytes = 4u * (size_t)S->slot_capacity;
         hz_status st = ctx_alloc(c, &sl.hits, sl.scratch_bytes);
+        if (st == HZ_OK) st = ctx_alloc(c, &sl.bins, (size_t)S->slot_capacity);
         if (st == HZ_OK) st = ctx_alloc(c, &sl.counters, kCounterBytes);
         if (st == HZ_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             st = set_error(HZ_E_DEVICE, "hz_server_start: hipStreamCreate failed");

@@ -14,8 +14,9 @@
 // Two launches per trace:
 //   k_raygen  one thread per queue slot: pinhole ray, slab test against the
 //             volume; rays that miss are finished at once, rays that enter
-//             are appended to a compact hit list (wave ballot + mbcnt + one
-//             atomic per wave)
+//             are binned by their chord length (longest first) and counted
+//   k_raygen_place  places the entering rays in a hit list sorted by bin
+//             (wave ballots + mbcnt ranks, one atomic per workgroup and bin)
 //   k_march   persistent waves pull hit rays from the list; when enough lanes
 //             have finished, the idle lanes are refilled together (ballot of
 //             idle lanes, one atomic per wave, mbcnt rank), which keeps the
@@ -97,8 +98,10 @@ __device__ __forceinline__ float3 pixel_dir(const TraceJob &J, int32_t p, int32_
     return make_float3(dx * inv, dy * inv, dz * inv);
 }
 
-// Slab test; on a hit returns the entry parameter clamped at 0.
-__device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3], const float d[3], float &t0)
+// Slab test; on a hit returns the entry parameter clamped at 0 (and the exit
+// parameter in t1 when asked).
+__device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3], const float d[3], float &t0,
+                                             float *t1 = nullptr)
 {
     float a = -INFINITY, b = INFINITY;
 #pragma unroll
@@ -114,6 +117,7 @@ __device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3
     }
     if (a > b || b <= 0.0f) return false;
     t0 = fmaxf(a, 0.0f);
+    if (t1) *t1 = b;
     return true;
 }
 
@@ -258,24 +262,42 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
     if (stat) stat[o] = (uint8_t)status;
 }
 
-// Zero the segment counts and the dynamic batch head.
+// Zero the bin totals, the placement cursors and the march batch head.
 __global__ void k_trace_init(uint32_t *counters)
 {
-    if (threadIdx.x <= kHitSegs) *hit_counter(counters, threadIdx.x) = 0u;
+    if (threadIdx.x <= kMarchHead) *hit_counter(counters, threadIdx.x) = 0u;
+}
+
+// Per-wave counts of each bin among the lanes' bins (255: none) into
+// wcnt[wave][bin]; returns the lane's rank among the wave's lanes of its bin.
+__device__ __forceinline__ uint32_t bin_rank(int bin, uint32_t (*wcnt)[kRayBins])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t rank = 0;
+#pragma unroll
+    for (int b = 0; b < kRayBins; ++b) {
+        const uint64_t m = __ballot(bin == b);
+        if (lane == 0) wcnt[wave][b] = (uint32_t)__popcll(m);
+        if (bin == b)
+            rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    }
+    return rank;
 }
 
 __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool enters = false;
+    int bin = 255;
     if (slot < L.nslots) {
         Ray r;
         if (decode_slot(L, slot, r)) {
             const TraceJob &J = L.jobs[r.job];
             const float3 d3 = pixel_dir(J, r.p, r.q);
             const float d[3] = {d3.x, d3.y, d3.z};
-            float t0;
-            enters = enter_volume(L.grid, J.eye, d, t0);
+            float t0, t1 = 0.0f;
+            enters = enter_volume(L.grid, J.eye, d, t0, &t1);
+            if (enters) bin = kRayBins - 1 - min(kRayBins - 1, max(0, (int)((t1 - t0) * L.inv_len_bin)));
             if (enters && L.nquads > 0) {
                 // a board in front of the volume ends the ray before it enters
                 float tq;
@@ -304,44 +326,44 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
             if (L.flat.surface) L.flat.surface[slot] = 255u;
         }
     }
-    // workgroup-aggregated append of the entering slots to this workgroup's
-    // segment: wave ballots, wave offsets in LDS, one atomic per workgroup
-    __shared__ uint32_t wcount[kRaygenBlock / 64];
-    __shared__ uint32_t wbase;
-    const uint64_t mask = __ballot(enters);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) wcount[wave] = (uint32_t)__popcll(mask);
+    // pass 1 of the length sort: remember the bin, count the bins of the
+    // workgroup (wave ballots), one atomic per non-empty bin
+    if (!enters) bin = 255;
+    if (slot < L.nslots) L.slot_bin[slot] = (uint8_t)bin;
+    __shared__ uint32_t wcnt[kRaygenBlock / 64][kRayBins];
+    bin_rank(bin, wcnt);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kRayBins) {
         uint32_t total = 0;
-        for (int w = 0; w < kRaygenBlock / 64; ++w) total += wcount[w];
-        wbase = total ? atomicAdd(hit_counter(L.counters, blockIdx.x % kHitSegs), total) : 0u;
-    }
-    __syncthreads();
-    if (enters) {
-        uint32_t off = wbase;
-        for (int w = 0; w < wave; ++w) off += wcount[w];
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        L.hits[(size_t)(blockIdx.x % kHitSegs) * L.seg_cap + off + rank] = (uint32_t)slot;
+        for (int w = 0; w < kRaygenBlock / 64; ++w) total += wcnt[w][threadIdx.x];
+        if (total) atomicAdd(hit_counter(L.counters, threadIdx.x), total);
     }
 }
 
-// Global hit index g -> slot, with the segments taken in order:
-// pre[k] = hits in segments before k (in LDS, read when a lane is refilled).
-__device__ __forceinline__ uint32_t hit_slot(const TraceLaunch &L, const uint32_t *pre, uint32_t g)
+// Pass 2 of the length sort: each entering ray takes its place in its bin's
+// range of the hit list (bins in order, longest rays first).  The order inside
+// a bin depends on the atomics, which changes no ray's result.
+__global__ __launch_bounds__(kRaygenBlock) void k_raygen_place(TraceLaunch L)
 {
-    int k = 0;
-    uint32_t base = 0;
-#pragma unroll
-    for (int j = 1; j < kHitSegs; ++j) {
-        const uint32_t p = pre[j];
-        if (g >= p) {
-            k = j;
-            base = p;
-        }
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int bin = slot < L.nslots ? (int)L.slot_bin[slot] : 255;
+    __shared__ uint32_t wcnt[kRaygenBlock / 64][kRayBins];
+    __shared__ uint32_t base[kRayBins];
+    const uint32_t rank = bin_rank(bin, wcnt);
+    __syncthreads();
+    if (threadIdx.x < kRayBins) {
+        const int b = threadIdx.x;
+        uint32_t total = 0, start = 0;
+        for (int w = 0; w < kRaygenBlock / 64; ++w) total += wcnt[w][b];
+        for (int k = 0; k < b; ++k) start += *hit_counter(L.counters, k);
+        base[b] = total ? start + atomicAdd(hit_counter(L.counters, kRayBins + b), total) : 0u;
     }
-    return L.hits[(size_t)k * L.seg_cap + (g - base)];
+    __syncthreads();
+    if (bin < kRayBins) {
+        uint32_t off = base[bin] + rank;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) off += wcnt[w][bin];
+        L.hits[off] = (uint32_t)slot;
+    }
 }
 
 __device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
@@ -472,29 +494,23 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 {
     const TraceGrid &G = L.grid;
     const TraceStep &S = L.step;
-    __shared__ uint32_t pre[kHitSegs + 1];
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int k = 0; k < kHitSegs; ++k) {
-            pre[k] = t;
-            t += *hit_counter(L.counters, k);
-        }
-        pre[kHitSegs] = t;
-    }
-    __syncthreads();
-    const uint32_t nh = __builtin_amdgcn_readfirstlane(pre[kHitSegs]);
+    uint32_t nh = 0;
+    for (int k = 0; k < kRayBins; ++k) nh += *hit_counter(L.counters, k);
+    nh = __builtin_amdgcn_readfirstlane(nh);
     const uint32_t refill_min = (uint32_t)max(1, min(64, L.refill_min));
     const int lane = threadIdx.x & 63;
 
-    // Work distribution.  Wave w first takes hits [64 w, 64 w + 64) with no
-    // atomic; later batches of 64 come from one counter past the static range,
-    // fetched one batch ahead (the atomic's latency hides behind the march).
-    // Each wave keeps its reserve [next, end) of hit indices.
+    // Work distribution over the length-sorted hits.  Wave w first takes
+    // hits [64 w, 64 w + 64) with no atomic; later batches of 64 come from one
+    // counter past the static range, fetched one batch ahead (the atomic's
+    // latency hides behind the march).  Each wave keeps its reserve
+    // [next, end) of hit indices.
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    const uint32_t dyn0 = nwaves * 64u;
-    uint32_t next = min(wave_id * 64u, nh);
-    uint32_t end = min(next + 64u, nh);
+    const uint32_t sb = 64u;
+    const uint32_t dyn0 = nwaves * sb;
+    uint32_t next = min(wave_id * sb, nh);
+    uint32_t end = min(next + sb, nh);
     bool done = next >= nh && dyn0 >= nh;
     bool pending = false;
     uint32_t pend_v = 0;
@@ -521,7 +537,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                     pending = false;
                 } else {
                     uint32_t v = 0;
-                    if (lane == 0) v = dyn0 + atomicAdd(hit_counter(L.counters, kHitSegs), 64u);
+                    if (lane == 0) v = dyn0 + atomicAdd(hit_counter(L.counters, kMarchHead), 64u);
                     b = __shfl(v, 0);
                 }
                 b = __builtin_amdgcn_readfirstlane(b);
@@ -536,7 +552,7 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                 const uint32_t k = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 if (k < end) {
-                    const int64_t slot = hit_slot(L, pre, k);
+                    const int64_t slot = L.hits[k];
                     decode_slot(L, slot, r);
                     const TraceJob &J = L.jobs[r.job];
                     field = J.field;
@@ -563,8 +579,12 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
             }
             next = min(next + nidle, end);
             if (next == end && !pending) {
-                if (lane == 0) pend_v = dyn0 + atomicAdd(hit_counter(L.counters, kHitSegs), 64u);
-                pending = true;
+                if (dyn0 >= nh) {
+                    done = true;   // the static batches hold every hit: no dynamic work
+                } else {
+                    if (lane == 0) pend_v = dyn0 + atomicAdd(hit_counter(L.counters, kMarchHead), 64u);
+                    pending = true;
+                }
             }
             continue;
         }
@@ -671,9 +691,11 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s)
 {
     hipLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, L.counters);
-    if (L.nslots > 0)
-        hipLaunchKernelGGL(k_raygen, dim3((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock)),
-                           dim3(kRaygenBlock), 0, s, L);
+    if (L.nslots > 0) {
+        const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
+        hipLaunchKernelGGL(k_raygen, g, dim3(kRaygenBlock), 0, s, L);
+        hipLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, L);
+    }
     return hipGetLastError();
 }
 
