@@ -136,7 +136,7 @@ struct TraceLaunch {
 // kCounterStride words (256 B) apart so that no two share a cache line:
 // bin totals [0, kRayBins), placement cursors [kRayBins, 2 kRayBins), and the
 // march's dynamic batch head at 2 kRayBins.
-constexpr int kRayBins = 16;
+constexpr int kRayBins = 32;
 constexpr int kCounterStride = 64;
 constexpr int kRaygenBlock = 256;
 constexpr int kMarchHead = 2 * kRayBins;

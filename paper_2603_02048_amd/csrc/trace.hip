@@ -265,7 +265,7 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
 // Zero the bin totals, the placement cursors and the march batch head.
 __global__ void k_trace_init(uint32_t *counters)
 {
-    if (threadIdx.x <= kMarchHead) *hit_counter(counters, threadIdx.x) = 0u;
+    for (int k = threadIdx.x; k <= kMarchHead; k += blockDim.x) *hit_counter(counters, k) = 0u;
 }
 
 // Per-wave counts of each bin among the lanes' bins (255: none) into

@@ -156,6 +156,33 @@ def test_trace_subset_and_repeatability(ctx, haze):
     field.release()
 
 
+def test_trace_repeated_calls_reset_the_queue(ctx, haze):
+    # few march waves (one workgroup per CU) and many rays, so most rays come
+    # from the dynamic batches: every call must start from a fresh queue
+    wl = W.make_small(seed=8, width=256, height=192, nviews=8, radius=0.9).with_k_gd(50.0)
+    parts = haze.upload_particles(wl.particles)
+    field = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+    ctx.tune("march.blocks_per_cu", 1)
+    try:
+        a1 = to_np(ctx.trace_views(field, wl.views, wl.step_adaptive))
+        u1 = to_np(ctx.trace_views(field, wl.views, wl.step_uniform))
+        a2 = to_np(ctx.trace_views(field, wl.views, wl.step_adaptive))
+        u2 = to_np(ctx.trace_views(field, wl.views, wl.step_uniform))
+    finally:
+        ctx.tune("march.blocks_per_cu", 0)
+    hits = int((a1["steps"] > 0).sum())
+    print(f"repeated calls: {hits} rays in the volume", flush=True)
+    assert hits > 4 * 256 * 64        # well past the static batches of 1024 waves
+    for x, y in ((a1, a2), (u1, u2)):
+        for k in x:
+            assert np.array_equal(x[k].view(np.uint8), y[k].view(np.uint8)), k
+    # and the same as a default launch shape
+    a3 = to_np(ctx.trace_views(field, wl.views, wl.step_adaptive))
+    for k in a1:
+        assert np.array_equal(a1[k].view(np.uint8), a3[k].view(np.uint8)), k
+    field.release()
+
+
 def test_trace_bad_ray_ids_flagged(ctx, haze):
     wl = W.make_small(seed=5, width=9, height=8, nviews=1)
     field, _ = _splat_both(ctx, haze, wl)
