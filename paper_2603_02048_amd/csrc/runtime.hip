@@ -109,7 +109,7 @@ struct hz_ctx {
     std::atomic<uint64_t> used{0};
     std::mutex ledger_mu;
     // splat scratch
-    Scratch cid, count, start, cursor, slots, sorted, dn, tiles;
+    Scratch cid, count, start, lrank, slots, sorted, dn, tiles;
     // trace scratch
     Scratch jobs, hits, bins, counters;
     std::vector<PinnedSlot> pinned;
@@ -412,7 +412,7 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
         for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
         c->prof_free.clear();
     }
-    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->jobs,
+    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->lrank, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->jobs,
                        &c->hits, &c->bins, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
@@ -607,9 +607,9 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     hipStream_t s = (hipStream_t)hip_stream;
     const int32_t n = (int32_t)P->n;
     const int64_t nv = (int64_t)g->res[0] * g->res[1] * g->res[2];
-    Scratch *bufs[8] = {&c->cid, &c->count, &c->start, &c->cursor, &c->slots, &c->sorted, &c->dn, &c->tiles};
+    Scratch *bufs[8] = {&c->cid, &c->count, &c->start, &c->lrank, &c->slots, &c->sorted, &c->dn, &c->tiles};
     const size_t sizes[8] = {4u * (size_t)n, 4u * (size_t)(ncells + 2), 4u * (size_t)(ncells + 1),
-                             4u * (size_t)(ncells + 1), 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv,
+                             4u * (size_t)n, 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv,
                              4u * (size_t)scan_tiles((int32_t)ncells)};
     for (int i = 0; i < 8; ++i) {
         st = scratch_acquire(c, *bufs[i], sizes[i], s);
@@ -625,7 +625,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
 
     hipEvent_t t0 = prof_begin(c, s);
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
-                                    (uint32_t *)c->start.ptr, (uint32_t *)c->cursor.ptr, (uint32_t *)c->slots.ptr,
+                                    (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr, (uint32_t *)c->slots.ptr,
                                     (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s);
     prof_end(c, s, "cell_list", t0);
     if (e == hipSuccess) {

@@ -10,9 +10,10 @@
 //                  by 2h), integer histogram with atomics
 //   k_scan_*       exclusive prefix sum of the histogram (tile sums, scan of
 //                  the tile sums, tiles rescanned with their offsets)
-//   k_cell_scatter particle index -> a slot of its cell (arbitrary order)
-//   k_cell_order   per cell, rank the slots by particle index (stable order)
-//                  and gather (x, y, z, m) into cell-sorted float4 records
+//   k_cell_scatter particle index -> its slot (cell start + arrival rank from
+//                  the histogram atomics: an arbitrary order inside the cell)
+//   k_cell_order   per particle, its rank by index among its cell's members
+//                  (stable order); (x, y, z, m) into cell-sorted float4 records
 //   k_splat        one wave per 8x8x4 voxel brick: every lane owns a column of
 //                  4 voxels and all lanes walk the same candidate particles
 //                  (wave-uniform scalar loads) row by row of the cell list,
@@ -43,8 +44,10 @@ __device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, in
     return (int)c;
 }
 
-// Particle -> cell id (0xffffffff when outside the grown box) + histogram.
-// With MMAX, also records max |m| of the binned particles (as float bits;
+// Particle -> cell id (0xffffffff when outside the grown box) + histogram;
+// the atomic's old value is the particle's arrival rank in its cell (an
+// arbitrary order that k_cell_order replaces by index order).  With MMAX,
+// also records max |m| of the binned particles (as float bits;
 // non-negative floats order like unsigned integers) in *mmax for the
 // fixed-point splat: reduced over the workgroup first, so one atomic per
 // workgroup reaches the single address.
@@ -52,7 +55,8 @@ template <bool MMAX>
 __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x, const float *__restrict__ y,
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
-                                                    uint32_t *__restrict__ count, uint32_t *__restrict__ mmax)
+                                                    uint32_t *__restrict__ lrank, uint32_t *__restrict__ count,
+                                                    uint32_t *__restrict__ mmax)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t mbits = 0u;
@@ -63,7 +67,7 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
         uint32_t id = 0xffffffffu;
         if (cx >= 0 && cy >= 0 && cz >= 0) {
             id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
-            atomicAdd(&count[id], 1u);
+            lrank[i] = atomicAdd(&count[id], 1u);
             if (MMAX) {
                 const float am = fabsf(m[i]);
                 if (am > 0.0f && isfinite(am)) mbits = __float_as_uint(am);
@@ -163,37 +167,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *__r
     }
 }
 
-// Every binned particle takes a slot of its cell.
-__global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict__ cid, int32_t n,
-                                                      uint32_t *__restrict__ cursor, uint32_t *__restrict__ slots)
+// Every binned particle takes the slot of its cell given by its arrival rank.
+__global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict__ cid,
+                                                      const uint32_t *__restrict__ lrank, int32_t n,
+                                                      const uint32_t *__restrict__ start,
+                                                      uint32_t *__restrict__ slots)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
-    uint32_t pos = atomicAdd(&cursor[c], 1u);
-    slots[pos] = (uint32_t)i;
+    slots[start[c] + lrank[i]] = (uint32_t)i;
 }
 
-// One wave per cell: the rank of a particle inside its cell is the number of
-// cell members with a smaller index, which puts each cell in index order
-// whatever order k_cell_scatter produced.
-__global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__ start,
-                                                    const uint32_t *__restrict__ slots, int32_t ncells,
+// One thread per particle: its rank inside its cell is the number of cell
+// members with a smaller index, which puts each cell in index order whatever
+// order the arrival ranks gave; the particle's (x, y, z, m) record goes there.
+__global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__ cid,
+                                                    const uint32_t *__restrict__ start,
+                                                    const uint32_t *__restrict__ slots, int32_t n,
                                                     const float *__restrict__ x, const float *__restrict__ y,
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     float4 *__restrict__ sorted)
 {
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= ncells) return;
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = cid[i];
+    if (c == 0xffffffffu) return;
     const uint32_t b = start[c], e = start[c + 1];
-    for (uint32_t s = b + lane; s < e; s += 64) {
-        const uint32_t me = slots[s];
-        uint32_t rank = 0;
-        for (uint32_t t = b; t < e; ++t) rank += slots[t] < me ? 1u : 0u;
-        sorted[b + rank] = make_float4(x[me], y[me], z[me], m[me]);
-    }
+    uint32_t rank = 0;
+    for (uint32_t t = b; t < e; ++t) rank += slots[t] < (uint32_t)i ? 1u : 0u;
+    sorted[b + rank] = make_float4(x[i], y[i], z[i], m[i]);
 }
 
 // Adds one candidate particle's M4-spline terms to the lane's column of voxels.
@@ -565,7 +569,7 @@ static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t -
 int32_t scan_tiles(int32_t ncells) { return (ncells + SCAN_TILE - 1) / SCAN_TILE; }
 
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
-                            const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *cursor,
+                            const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *lrank,
                             uint32_t *slots, float4 *sorted, uint32_t *tile_sum, bool want_mmax, hipStream_t s)
 {
     // count[ncells + 1] holds max |m| (scatter splat only); both start at zero
@@ -573,20 +577,18 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
                        (int64_t)cg.ncells + 2);
     if (want_mmax)
         hipLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
-                           count, count + cg.ncells + 1);
+                           lrank, count, count + cg.ncells + 1);
     else
         hipLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
-                           count, count + cg.ncells + 1);
+                           lrank, count, count + cg.ncells + 1);
     const int32_t ntiles = (cg.ncells + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum);
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles, start + cg.ncells);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum,
                        start);
-    hipError_t e = hipMemcpyAsync(cursor, start, sizeof(uint32_t) * (size_t)cg.ncells, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, n, cursor, slots);
-    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(cg.ncells, 4)), dim3(256), 0, s, start, slots, cg.ncells, x, y,
-                       z, m, sorted);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots);
+    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, start, slots, n, x, y, z, m,
+                       sorted);
     return hipGetLastError();
 }
 
