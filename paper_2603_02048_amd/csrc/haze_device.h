@@ -7,6 +7,13 @@
 
 namespace haze {
 
+// Timing events of a group of launches: the first launch records `start` when
+// it begins and the last records `stop` when it ends (AMD dispatch-packet
+// timestamps, no extra packets in the stream); null when profiling is off.
+struct KTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---------------------------------------------------------------------------
 // splat: particle cell list and brick gather
 // ---------------------------------------------------------------------------

@@ -24,17 +24,18 @@
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
                             uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, uint32_t *, bool,
-                            hipStream_t);
+                            hipStream_t, const KTimer &);
 int32_t scan_tiles(int32_t ncells);
-hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t);
+hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t, const KTimer &);
 hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const float4 *, const uint32_t *, float *,
-                                hipStream_t);
+                                hipStream_t, const KTimer &);
 int scatter_max_rows(const SplatParams &P);
 int scatter_rows_limit();
-hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t);
+hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t,
+                            const KTimer &);
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
-hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
-hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t);
+hipError_t launch_raygen(const TraceLaunch &, hipStream_t, const KTimer &);
+hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 int march_blocks_per_cu(int, int);
 }  // namespace haze
 
@@ -320,10 +321,10 @@ static uint64_t pool_bytes(hz_ctx *c)
 // ---------------------------------------------------------------------------
 // per-kernel event timing
 // ---------------------------------------------------------------------------
-static hipEvent_t prof_begin(hz_ctx *c, hipStream_t s)
+// Kernels are timed by the events their dispatch packets record (no marker
+// packets between kernels, so profiling does not stretch the stream).
+static hipEvent_t prof_event_locked(hz_ctx *c)
 {
-    if (!c->prof_on) return nullptr;
-    std::lock_guard<std::mutex> g(c->prof_mu);
     hipEvent_t e = nullptr;
     if (!c->prof_free.empty()) {
         e = c->prof_free.back();
@@ -331,8 +332,23 @@ static hipEvent_t prof_begin(hz_ctx *c, hipStream_t s)
     } else if (hipEventCreate(&e) != hipSuccess) {
         return nullptr;
     }
-    if (hipEventRecord(e, s) != hipSuccess) return nullptr;
     return e;
+}
+
+// A start/stop pair for a group of launches, or nulls when profiling is off.
+static KTimer prof_timer(hz_ctx *c)
+{
+    KTimer t;
+    if (!c->prof_on) return t;
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    t.start = prof_event_locked(c);
+    t.stop = prof_event_locked(c);
+    if (!t.start || !t.stop) {
+        if (t.start) c->prof_free.push_back(t.start);
+        if (t.stop) c->prof_free.push_back(t.stop);
+        return KTimer{};
+    }
+    return t;
 }
 
 static void prof_flush_locked(hz_ctx *c)
@@ -350,24 +366,12 @@ static void prof_flush_locked(hz_ctx *c)
     c->prof_pending.clear();
 }
 
-static void prof_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a)
+// Queue a launched timer's pair for accumulation under `name`.
+static void prof_commit(hz_ctx *c, const char *name, const KTimer &t)
 {
-    if (!a) return;
+    if (!t.start) return;
     std::lock_guard<std::mutex> g(c->prof_mu);
-    hipEvent_t b = nullptr;
-    if (!c->prof_free.empty()) {
-        b = c->prof_free.back();
-        c->prof_free.pop_back();
-    } else if (hipEventCreate(&b) != hipSuccess) {
-        c->prof_free.push_back(a);
-        return;
-    }
-    if (hipEventRecord(b, s) != hipSuccess) {
-        c->prof_free.push_back(a);
-        c->prof_free.push_back(b);
-        return;
-    }
-    c->prof_pending.push_back({name, a, b});
+    c->prof_pending.push_back({name, t.start, t.stop});
     if (c->prof_pending.size() > 65536) prof_flush_locked(c);
 }
 
@@ -547,9 +551,9 @@ static hz_status pack_field(hz_ctx *c, const float *dn, const hz_grid *g, hz_fie
     int32_t res[3] = {g->res[0], g->res[1], g->res[2]};
     float inv_sp[3];
     for (int a = 0; a < 3; ++a) inv_sp[a] = (float)((double)g->res[a] / (g->hi[a] - g->lo[a]));
-    hipEvent_t t0 = prof_begin(c, s);
-    HZ_HIP(launch_grad_pack((int)f->dtype, dn, res, inv_sp, f->store_scale, f->data, s), "grad/pack launch");
-    prof_end(c, s, "grad_pack", t0);
+    const KTimer t = prof_timer(c);
+    HZ_HIP(launch_grad_pack((int)f->dtype, dn, res, inv_sp, f->store_scale, f->data, s, t), "grad/pack launch");
+    prof_commit(c, "grad_pack", t);
     return HZ_OK;
 }
 
@@ -623,20 +627,20 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
     if (st != HZ_OK) return st;
 
-    hipEvent_t t0 = prof_begin(c, s);
+    const KTimer t0 = prof_timer(c);
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr, (uint32_t *)c->slots.ptr,
-                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s);
-    prof_end(c, s, "cell_list", t0);
+                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s, t0);
+    prof_commit(c, "cell_list", t0);
     if (e == hipSuccess) {
-        hipEvent_t t1 = prof_begin(c, s);
+        const KTimer t1 = prof_timer(c);
         if (scatter)
             e = launch_splat_scatter(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr,
-                                     (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, s);
+                                     (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, s, t1);
         else
             e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr,
-                             s);
-        prof_end(c, s, "splat", t1);
+                             s, t1);
+        prof_commit(c, "splat", t1);
     }
     if (e != hipSuccess) {
         field_destroy(f);
@@ -1007,12 +1011,12 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
     blocks64 = std::max<int64_t>(1, blocks64);
     const int blocks = (int)blocks64;
-    hipEvent_t t0 = prof_begin(c, s);
-    HZ_HIP(launch_raygen(L, s), "raygen launch");
-    prof_end(c, s, "raygen", t0);
-    hipEvent_t t1 = prof_begin(c, s);
-    HZ_HIP(launch_march(dt, L, blocks, s), "march launch");
-    prof_end(c, s, "march", t1);
+    const KTimer t0 = prof_timer(c);
+    HZ_HIP(launch_raygen(L, s, t0), "raygen launch");
+    prof_commit(c, "raygen", t0);
+    const KTimer t1 = prof_timer(c);
+    HZ_HIP(launch_march(dt, L, blocks, s, t1), "march launch");
+    prof_commit(c, "march", t1);
     scratch_release(c->jobs, s);
     scratch_release(c->hits, s);
     scratch_release(c->bins, s);
@@ -1048,7 +1052,7 @@ const void *field_data(const hz_field *f) { return f->data; }
 hz_ctx *field_ctx(const hz_field *f) { return f->ctx; }
 hz_status field_use(hz_field *f, hipStream_t s) { return field_mark_used(f, s); }
 int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
-hipEvent_t profile_begin(hz_ctx *c, hipStream_t s) { return prof_begin(c, s); }
-void profile_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a) { prof_end(c, s, name, a); }
+KTimer profile_timer(hz_ctx *c) { return prof_timer(c); }
+void profile_commit(hz_ctx *c, const char *name, const KTimer &t) { prof_commit(c, name, t); }
 hz_status set_error(hz_status s, const char *msg) { return fail(s, "%s", msg); }
 }  // namespace haze

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "haze.h"
+#include "haze_device.h"
 
 #include <hip/hip_runtime.h>
 
@@ -23,7 +24,7 @@ const void *field_data(const hz_field *f);
 hz_ctx *field_ctx(const hz_field *f);
 hz_status field_use(hz_field *f, hipStream_t s);
 int march_blocks(hz_ctx *c, int dt);
-hipEvent_t profile_begin(hz_ctx *c, hipStream_t s);
-void profile_end(hz_ctx *c, hipStream_t s, const char *name, hipEvent_t a);
+KTimer profile_timer(hz_ctx *c);
+void profile_commit(hz_ctx *c, const char *name, const KTimer &t);
 hz_status set_error(hz_status s, const char *msg);
 }  // namespace haze

@@ -27,8 +27,8 @@
 #include <vector>
 
 namespace haze {
-hipError_t launch_raygen(const TraceLaunch &, hipStream_t);
-hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t);
+hipError_t launch_raygen(const TraceLaunch &, hipStream_t, const KTimer &);
+hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 hz_status check_step(const hz_step *st, const char *fn);
 hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
                    const char *fn, int index);
@@ -190,10 +190,11 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.refill_min = 16;
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
-    hipEvent_t t0 = profile_begin(S->ctx, sl.stream);
-    if (launch_raygen(L, sl.stream) != hipSuccess || launch_march(dt, L, blocks, sl.stream) != hipSuccess)
+    const KTimer t = profile_timer(S->ctx);
+    if (launch_raygen(L, sl.stream, KTimer{t.start, nullptr}) != hipSuccess ||
+        launch_march(dt, L, blocks, sl.stream, KTimer{nullptr, t.stop}) != hipSuccess)
         return set_error(HZ_E_DEVICE, "serve: trace launch failed");
-    profile_end(S->ctx, sl.stream, "serve_batch", t0);
+    profile_commit(S->ctx, "serve_batch", t);
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
     for (Request *r : batch) {
         field_use(r->field, sl.stream);

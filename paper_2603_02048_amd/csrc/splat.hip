@@ -27,6 +27,7 @@
 //                  (delta_n, grad) into F32 / F16 / BF16 voxels
 #include "haze_device.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 namespace haze {
@@ -463,14 +464,14 @@ int scatter_max_rows(const SplatParams &P)
 int scatter_rows_limit() { return SC_MAXROWS; }
 
 hipError_t launch_splat_scatter(const SplatParams &P, const uint32_t *start, const float4 *sorted,
-                                const uint32_t *mmax_bits, float *dn, hipStream_t s)
+                                const uint32_t *mmax_bits, float *dn, hipStream_t s, const KTimer &t)
 {
     const int32_t ntx = (P.res[0] + SC_TX - 1) / SC_TX, nty = (P.res[1] + SC_TY - 1) / SC_TY,
                   ntz = (P.res[2] + SC_TZ - 1) / SC_TZ;
     const int32_t ntiles = ntx * nty * ntz;
     const int32_t per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL(k_splat_scatter, dim3((unsigned)(per_xcd * 8)), dim3(SC_THREADS), 0, s, P, start, sorted,
-                       mmax_bits, ntx, nty, ntiles, per_xcd, dn);
+    hipExtLaunchKernelGGL(k_splat_scatter, dim3((unsigned)(per_xcd * 8)), dim3(SC_THREADS), 0, s, t.start, t.stop, 0,
+                          P, start, sorted, mmax_bits, ntx, nty, ntiles, per_xcd, dn);
     return hipGetLastError();
 }
 
@@ -570,11 +571,12 @@ int32_t scan_tiles(int32_t ncells) { return (ncells + SCAN_TILE - 1) / SCAN_TILE
 
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *lrank,
-                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, bool want_mmax, hipStream_t s)
+                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, bool want_mmax, hipStream_t s,
+                            const KTimer &t)
 {
     // count[ncells + 1] holds max |m| (scatter splat only); both start at zero
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 2, 256)), dim3(256), 0, s, count, 0u,
-                       (int64_t)cg.ncells + 2);
+    hipExtLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 2, 256)), dim3(256), 0, s, t.start, nullptr, 0,
+                          count, 0u, (int64_t)cg.ncells + 2);
     if (want_mmax)
         hipLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
                            lrank, count, count + cg.ncells + 1);
@@ -587,35 +589,36 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum,
                        start);
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots);
-    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, start, slots, n, x, y, z, m,
-                       sorted);
+    hipExtLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, nullptr, t.stop, 0, cid, start,
+                          slots, n, x, y, z, m, sorted);
     return hipGetLastError();
 }
 
-hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn, hipStream_t s)
+hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn, hipStream_t s,
+                        const KTimer &t)
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
     const int32_t nblocks = (nbricks + 3) / 4;
     const int32_t per_xcd = (nblocks + 7) / 8;
-    hipLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, P, start, sorted, nbricks, per_xcd,
-                       dn);
+    hipExtLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, t.start, t.stop, 0, P, start,
+                          sorted, nbricks, per_xcd, dn);
     return hipGetLastError();
 }
 
 hipError_t launch_grad_pack(int dtype, const float *dn, const int32_t res[3], const float inv_sp[3], float scale,
-                            void *out, hipStream_t s)
+                            void *out, hipStream_t s, const KTimer &t)
 {
     const int64_t nv = (int64_t)res[0] * res[1] * res[2];
     const dim3 g(blocks_for(nv, 256)), b(256);
     if (dtype == DT_F32)
-        hipLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
-                           inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
+                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     else if (dtype == DT_F16)
-        hipLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
-                           inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
+                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     else
-        hipLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, dn, res[0], res[1], res[2], inv_sp[0], inv_sp[1],
-                           inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
+                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     return hipGetLastError();
 }
 

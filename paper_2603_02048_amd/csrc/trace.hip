@@ -31,6 +31,7 @@
 // of many small turns that a unit vector would round away.
 #include "haze_device.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 namespace haze {
@@ -688,36 +689,37 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 // host launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s)
+hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s, const KTimer &t)
 {
-    hipLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, L.counters);
+    hipExtLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, t.start, L.nslots > 0 ? nullptr : t.stop, 0,
+                          L.counters);
     if (L.nslots > 0) {
         const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
         hipLaunchKernelGGL(k_raygen, g, dim3(kRaygenBlock), 0, s, L);
-        hipLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, L);
+        hipExtLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, nullptr, t.stop, 0, L);
     }
     return hipGetLastError();
 }
 
 template <int SCENE>
-static void launch_march_t(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s)
+static void launch_march_t(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s, const KTimer &t)
 {
     if (dtype == DT_F32)
-        hipLaunchKernelGGL((k_march<DT_F32, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
+        hipExtLaunchKernelGGL((k_march<DT_F32, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
     else if (dtype == DT_F16)
-        hipLaunchKernelGGL((k_march<DT_F16, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
+        hipExtLaunchKernelGGL((k_march<DT_F16, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
     else
-        hipLaunchKernelGGL((k_march<DT_BF16, SCENE>), dim3(march_blocks), dim3(256), 0, s, L);
+        hipExtLaunchKernelGGL((k_march<DT_BF16, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
 }
 
-hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s)
+hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s, const KTimer &t)
 {
     if (L.ninner > 0)
-        launch_march_t<2>(dtype, L, march_blocks, s);
+        launch_march_t<2>(dtype, L, march_blocks, s, t);
     else if (L.nquads > 0)
-        launch_march_t<1>(dtype, L, march_blocks, s);
+        launch_march_t<1>(dtype, L, march_blocks, s, t);
     else
-        launch_march_t<0>(dtype, L, march_blocks, s);
+        launch_march_t<0>(dtype, L, march_blocks, s, t);
     return hipGetLastError();
 }
 
