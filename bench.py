@@ -177,10 +177,23 @@ def serving_leg(haze, torch, W, args) -> dict:
         ctx.close()
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, args) -> dict:
-    """The FP64 oracle on the host cores: full splat + a bounded ray sample."""
+    """The FP64 oracle on the host cores: full splat + a bounded ray sample,
+    then the same ray sample (a quarter of it) on one thread."""
     import oracle
     oracle.build()
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
     md = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h, "cells")
     t_splat = time.perf_counter() - t0
@@ -191,11 +204,23 @@ def cpu_baseline(wl, args) -> dict:
     r = oracle.trace_views(md, wl.views, wl.step_adaptive, ray_ids=ids)
     t_trace = time.perf_counter() - t0
     frame_s = t_splat + t_trace * wl.nrays / ns
-    return {"value": wl.nrays / frame_s, "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
+    oracle.set_num_threads(1)
+    try:
+        ids1 = ids[::4]
+        t0 = time.perf_counter()
+        r1 = oracle.trace_views(md, wl.views, wl.step_adaptive, ray_ids=ids1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": wl.nrays / frame_s, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle: full splat of the {tuple(int(x) for x in wl.grid.res)} grid "
                        f"({t_splat:.2f} s) + {ns} random rays of the {wl.nrays}-ray frame, adaptive "
                        f"({t_trace:.2f} s), scaled to one frame"),
-            "ray_steps_per_s": float(r["steps"].sum()) / t_trace, "frame_s": frame_s}
+            "ray_steps_per_s": float(r["steps"].sum()) / t_trace, "frame_s": frame_s,
+            "voxels_per_s": wl.grid.nvox / t_splat,
+            "single_thread": {"rays": int(ids1.size), "rays_per_s": ids1.size / t1,
+                              "ray_steps_per_s": float(r1["steps"].sum()) / t1},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main(argv=None):

@@ -114,6 +114,8 @@ def lib():
                                          P, P]
         L.ho_num_threads.restype = C.c_int
         L.ho_num_threads.argtypes = []
+        L.ho_set_num_threads.restype = None
+        L.ho_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -152,6 +154,10 @@ def _step(st) -> _Step:
 
 def num_threads() -> int:
     return int(lib().ho_num_threads())
+
+
+def set_num_threads(n: int):
+    lib().ho_set_num_threads(int(n))
 
 
 def kernel(r, h: float) -> np.ndarray:

@@ -918,3 +918,13 @@ int ho_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following calls (timing of the oracle itself). */
+void ho_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
