@@ -378,17 +378,20 @@ __device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
 // Trilinear (delta_n, g) at x: cell index clamped to [0, R-2], so the outer
 // half-voxel extrapolates linearly.
 template <int DT>
-__device__ __forceinline__ void cell_of(const TraceGrid &G, const float x[3], int64_t &b, float t[3])
+// (Fields hold fewer than 2^31 voxels, checked on the host: 32-bit indices.
+// A NaN coordinate converts to cell 0 and poisons the weights, which the
+// march's finiteness test catches.)
+__device__ __forceinline__ void cell_of(const TraceGrid &G, const float x[3], uint32_t &b, float t[3])
 {
-    int32_t i[3];
+    uint32_t i[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float u = fmaf(x[a], G.inv_sp[a], G.off[a]);
-        const float fl = fminf(fmaxf(floorf(u), 0.0f), G.maxi[a]);
-        i[a] = (int32_t)fl;
+        const float fl = __builtin_amdgcn_fmed3f(floorf(u), 0.0f, G.maxi[a]);
+        i[a] = (uint32_t)fl;
         t[a] = u - fl;
     }
-    b = ((int64_t)i[2] * G.res[1] + i[1]) * G.res[0] + i[0];
+    b = (i[2] * (uint32_t)G.res[1] + i[1]) * (uint32_t)G.res[0] + i[0];
 }
 
 // F16/BF16 voxels are 8 bytes; the two x-neighbours of a cell row are one
@@ -400,7 +403,7 @@ typedef const u32x4_a8 __attribute__((address_space(1))) *gpair_ptr;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef const f32x4 __attribute__((address_space(1))) *gfloat4_ptr;
 
-__device__ __forceinline__ float4 load_f32x4(gfloat4_ptr F, int64_t i)
+__device__ __forceinline__ float4 load_f32x4(gfloat4_ptr F, uint32_t i)
 {
     const f32x4 v = F[i];
     return make_float4(v.x, v.y, v.z, v.w);
@@ -421,9 +424,9 @@ __device__ __forceinline__ float4 half4_to_float4(uint32_t lo, uint32_t hi)
 }
 
 template <int DT>
-__device__ __forceinline__ void load_xpair(const void *__restrict__ f, int64_t i, float4 &a, float4 &b)
+__device__ __forceinline__ void load_xpair(const void *__restrict__ f, uint32_t i, float4 &a, float4 &b)
 {
-    const u32x4_a8 v = *(gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * i);
+    const u32x4_a8 v = *(gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * (size_t)i);
     a = half4_to_float4<DT>(v.x, v.y);
     b = half4_to_float4<DT>(v.z, v.w);
 }
@@ -431,10 +434,10 @@ __device__ __forceinline__ void load_xpair(const void *__restrict__ f, int64_t i
 template <int DT>
 __device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *__restrict__ f, const float x[3])
 {
-    int64_t b;
+    uint32_t b;
     float t[3];
     cell_of<DT>(G, x, b, t);
-    const int64_t sy = G.res[0], sz = (int64_t)G.res[0] * G.res[1];
+    const uint32_t sy = (uint32_t)G.res[0], sz = (uint32_t)G.res[0] * (uint32_t)G.res[1];
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
     if (DT == DT_F32) {
         gfloat4_ptr F = (gfloat4_ptr)f;
@@ -664,8 +667,9 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                     hp[0] = h[0]; hp[1] = h[1]; hp[2] = h[2];
                 }
             }
-            // any inf or nan among position, direction and n makes the sum non-finite
-            if (!isfinite(c[0] + c[1] + c[2] + w[0] + w[1] + w[2] + n))
+            // a non-finite sample makes n or the direction vector p non-finite
+            // (or p zero); otherwise the step, direction and position stay finite
+            if (!(pn2 > 0.0f && pn2 < INFINITY && fabsf(n) < INFINITY))
                 status = 3;
             else if (SCENE == 2 && surf >= 0) {
                 finish_ray<true>(L, r, hp, w, steps, 0, hp, surf);

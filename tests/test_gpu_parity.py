@@ -183,6 +183,28 @@ def test_trace_repeated_calls_reset_the_queue(ctx, haze):
     field.release()
 
 
+def test_trace_nonfinite_field(ctx, haze):
+    # a NaN voxel: rays whose samples touch it (directly or through the
+    # gradient's differences) end with status NONFINITE and NaN displacement,
+    # as in the oracle; every other ray is unaffected
+    grid = W.make_grid((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (24, 24, 24))
+    dn = W.analytic_grid_gauss(grid, 2e-3, (0.5, 0.5, 0.5), 0.2)
+    dn[12, 11, 10] = np.nan
+    f = ctx.index_field_from_grid(torch.from_numpy(dn.astype(np.float32)).cuda(), grid)
+    md = oracle.Medium.from_grid(grid, dn.astype(np.float32).astype(np.float64))
+    views = [W.ring_view(grid.lo, grid.hi, 0.0, 2.0, 48, 48, vfov_deg=35.0)]
+    for st in W.make_steps(grid):
+        out = to_np(ctx.trace_views(f, views, st))
+        ref = oracle.trace_views(md, views, st)
+        bad = ref["status"] == W.STATUS_NONFINITE
+        assert bad.sum() > 5 and (~bad).sum() > 1000
+        assert np.array_equal(out["status"], ref["status"])
+        assert np.isnan(out["disp"][bad]).all()
+        good = {k: v[~bad] for k, v in out.items()}
+        assert_rays_match(good, {k: v[~bad] for k, v in ref.items()}, grid.voxel, f"nonfinite uniform={st.uniform}")
+    f.release()
+
+
 def test_trace_bad_ray_ids_flagged(ctx, haze):
     wl = W.make_small(seed=5, width=9, height=8, nviews=1)
     field, _ = _splat_both(ctx, haze, wl)
