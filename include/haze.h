@@ -103,7 +103,7 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *                          idle, 1..64 (default 16)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
- *   "splat.method"         0 or 1: gather (one wave per 4x4x4 voxel brick,
+ *   "splat.method"         0 or 1: gather (one wave per 8x8x4 voxel brick,
  *                          fixed FP32 summation order; the default), 2: scatter
  *                          (voxel tiles with 64-bit fixed-point accumulation in
  *                          LDS; slower, for a support of up to ~16 cells per
@@ -112,11 +112,13 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  * Errors: HZ_E_INVALID (unknown key or value out of range). */
 hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 
-/* Per-kernel timing with HIP events recorded around every launch the context
- * makes on the caller's stream (kernels: "cell_list", "splat", "grad_pack",
- * "raygen", "march"; the serving loop's launches as "serve_batch").  hz_profile_read waits for the recorded
- * events and returns the summed milliseconds and launch count of `kernel`
- * since the last reset (reset != 0 clears all sums after reading). */
+/* Per-kernel timing with HIP events that the launches themselves record (the
+ * start of a group's first kernel, the end of its last), on the caller's
+ * stream; groups: "cell_list", "splat", "grad_pack", "raygen" (ray generation
+ * and the length sort), "march"; the serving loop's launches as
+ * "serve_batch".  hz_profile_read waits for the recorded events and returns the
+ * summed milliseconds and launch count of `kernel` since the last reset
+ * (reset != 0 clears all sums after reading). */
 hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);
 hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int32_t reset);
 
