@@ -349,14 +349,16 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen_place(TraceLaunch L)
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int bin = slot < L.nslots ? (int)L.slot_bin[slot] : 255;
     __shared__ uint32_t wcnt[kRaygenBlock / 64][kRayBins];
+    __shared__ uint32_t tot[kRayBins];
     __shared__ uint32_t base[kRayBins];
+    if (threadIdx.x < kRayBins) tot[threadIdx.x] = *hit_counter(L.counters, threadIdx.x);
     const uint32_t rank = bin_rank(bin, wcnt);
     __syncthreads();
     if (threadIdx.x < kRayBins) {
         const int b = threadIdx.x;
         uint32_t total = 0, start = 0;
         for (int w = 0; w < kRaygenBlock / 64; ++w) total += wcnt[w][b];
-        for (int k = 0; k < b; ++k) start += *hit_counter(L.counters, k);
+        for (int k = 0; k < b; ++k) start += tot[k];
         base[b] = total ? start + atomicAdd(hit_counter(L.counters, kRayBins + b), total) : 0u;
     }
     __syncthreads();
