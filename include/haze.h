@@ -120,6 +120,11 @@ hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
  * summed milliseconds and launch count of `kernel` since the last reset
  * (reset != 0 clears all sums after reading). */
 hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);
+/* Time only the listed groups (comma-separated names as above; NULL or ""
+ * selects all, the default).  Each timed group costs its stream a few
+ * microseconds per launch, so a run that needs one kernel's time selects it
+ * alone.  Errors: HZ_E_INVALID (unknown group name). */
+hz_status hz_profile_select(hz_ctx *ctx, const char *groups);
 hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int32_t reset);
 
 /* Achievable read bandwidth (GB/s) of a device buffer of `bytes` read `reps`

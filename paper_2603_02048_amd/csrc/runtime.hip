@@ -74,22 +74,22 @@ extern "C" const char *hz_last_error(void) { return g_err.c_str(); }
 // context, ledger and scratch
 // ---------------------------------------------------------------------------
 
-// A device buffer reused across calls.  `last_use` orders a reuse on another
-// stream after the previous user's work.
+// A device buffer reused across calls.  `last` is the ticket of the call that
+// used it last: a reuse on another stream, or freeing it, waits for that.
 struct Scratch {
     void *ptr = nullptr;
     size_t cap = 0;
-    hipEvent_t last_use = nullptr;
-    hipStream_t last_stream = nullptr;
-    bool used = false;
+    Ticket last;
 };
 
 struct PinnedSlot {
     void *host = nullptr;
     size_t cap = 0;
-    hipEvent_t done = nullptr;
-    bool used = false;
+    Ticket last;
 };
+
+// Events of the completion tickets (a ring; see ticket_issue).
+constexpr uint64_t kTicketRing = 64;
 
 struct hz_field {
     hz_ctx *ctx = nullptr;
@@ -98,8 +98,8 @@ struct hz_field {
     hz_grid grid{};
     hz_dtype dtype = HZ_F32;
     float store_scale = 1.0f;
-    hipEvent_t last_use = nullptr;
-    bool used = false;
+    Ticket made;                 // the call that wrote the field
+    std::vector<Ticket> uses;    // the latest call on each stream that touched it
     std::mutex mu;
 };
 
@@ -115,6 +115,9 @@ struct hz_ctx {
     Scratch jobs, hits, bins, counters;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
+    hipEvent_t tickets[kTicketRing] = {};
+    uint64_t ticket_next = 1;
+    std::mutex ticket_mu;
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
     int march_bpc_scene[2][3] = {};      // by board mode (outer / inner) and dtype
     // march tuning (hz_ctx_tune)
@@ -127,7 +130,7 @@ struct hz_ctx {
     struct PoolBlock {
         void *ptr;
         size_t bytes;
-        hipEvent_t ready;   // recorded after the block's last use
+        std::vector<Ticket> uses;   // the block's last use on each stream
     };
     std::vector<PoolBlock> pool;
     std::mutex pool_mu;
@@ -137,6 +140,7 @@ struct hz_ctx {
         hipEvent_t a, b;
     };
     bool prof_on = false;
+    std::vector<std::string> prof_only;   // empty: every group
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_free;
     std::map<std::string, std::pair<double, int64_t>> prof_acc;
@@ -201,13 +205,77 @@ uint64_t ctx_mem_avail(const hz_ctx *c)
 int ctx_num_cus(const hz_ctx *c) { return c->num_cus; }
 }  // namespace haze
 
+// ---------------------------------------------------------------------------
+// completion tickets
+// ---------------------------------------------------------------------------
+// Each call that enqueues work records ONE event after its last launch, its
+// ticket, and stamps every buffer and field it used with it.  A later call
+// orders itself after a ticket only when it runs on another stream or must
+// free the memory; on the same stream the order is already there.  (An event
+// record is a marker packet that costs the stream microseconds, so one per
+// call rather than one per buffer.)  The events form a ring: issuing ticket q
+// first waits for ticket q - kTicketRing, so a ticket whose event has been
+// recorded again is known to be complete.
+static hz_status ticket_issue(hz_ctx *c, hipStream_t s, Ticket *out)
+{
+    std::lock_guard<std::mutex> g(c->ticket_mu);
+    const uint64_t q = c->ticket_next;
+    hipEvent_t &e = c->tickets[q % kTicketRing];
+    if (!e)
+        HZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    else
+        HZ_HIP(hipEventSynchronize(e), "hipEventSynchronize");
+    HZ_HIP(hipEventRecord(e, s), "hipEventRecord");
+    c->ticket_next = q + 1;
+    *out = Ticket{q, s};
+    return HZ_OK;
+}
+
+// The event still holding ticket t, or null when t is known to be complete.
+static hipEvent_t ticket_event_locked(hz_ctx *c, const Ticket &t)
+{
+    if (t.seq == 0 || t.seq + kTicketRing < c->ticket_next) return nullptr;
+    return c->tickets[t.seq % kTicketRing];
+}
+
+// Order `stream` after ticket t.
+static hz_status ticket_wait(hz_ctx *c, const Ticket &t, hipStream_t stream)
+{
+    if (t.seq == 0 || t.stream == stream) return HZ_OK;
+    std::lock_guard<std::mutex> g(c->ticket_mu);
+    hipEvent_t e = ticket_event_locked(c, t);
+    if (e && hipEventQuery(e) != hipSuccess) HZ_HIP(hipStreamWaitEvent(stream, e, 0), "hipStreamWaitEvent");
+    return HZ_OK;
+}
+
+// Whether ticket t's work is known to be done (a query; never waits).
+static bool ticket_done(hz_ctx *c, const Ticket &t)
+{
+    std::lock_guard<std::mutex> g(c->ticket_mu);
+    hipEvent_t e = ticket_event_locked(c, t);
+    return !e || hipEventQuery(e) == hipSuccess;
+}
+
+// Block the host until ticket t's work is done.  Should the event be recorded
+// again meanwhile, its issuer has already waited for t.
+static hz_status ticket_sync(hz_ctx *c, const Ticket &t)
+{
+    hipEvent_t e;
+    {
+        std::lock_guard<std::mutex> g(c->ticket_mu);
+        e = ticket_event_locked(c, t);
+    }
+    if (e) HZ_HIP(hipEventSynchronize(e), "hipEventSynchronize");
+    return HZ_OK;
+}
+
 // Make `s` at least `bytes` large and order its use on `stream` after its
 // previous use.  Growing waits for the previous user before freeing.
 static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_t stream)
 {
-    if (!s.last_use) HZ_HIP(hipEventCreateWithFlags(&s.last_use, hipEventDisableTiming), "hipEventCreate");
     if (s.cap < bytes) {
-        if (s.used) HZ_HIP(hipEventSynchronize(s.last_use), "hipEventSynchronize");
+        hz_status st = ticket_sync(c, s.last);
+        if (st != HZ_OK) return st;
         if (s.ptr) {
             ctx_free(c, s.ptr, s.cap);
             s.ptr = nullptr;
@@ -215,28 +283,18 @@ static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_
         }
         size_t want = std::max<size_t>(bytes, 4096);
         want = (want + 4095) & ~(size_t)4095;
-        hz_status st = ctx_alloc(c, &s.ptr, want);
+        st = ctx_alloc(c, &s.ptr, want);
         if (st != HZ_OK) return st;
         s.cap = want;
-    } else if (s.used && s.last_stream != stream) {
-        HZ_HIP(hipStreamWaitEvent(stream, s.last_use, 0), "hipStreamWaitEvent");
+        return HZ_OK;
     }
-    return HZ_OK;
-}
-
-static hz_status scratch_release(Scratch &s, hipStream_t stream)
-{
-    HZ_HIP(hipEventRecord(s.last_use, stream), "hipEventRecord");
-    s.last_stream = stream;
-    s.used = true;
-    return HZ_OK;
+    return ticket_wait(c, s.last, stream);
 }
 
 static void scratch_free(hz_ctx *c, Scratch &s)
 {
-    if (s.used && s.last_use) (void)hipEventSynchronize(s.last_use);
+    (void)ticket_sync(c, s.last);
     if (s.ptr) ctx_free(c, s.ptr, s.cap);
-    if (s.last_use) (void)hipEventDestroy(s.last_use);
     s = Scratch{};
 }
 
@@ -271,24 +329,23 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
 
 static void field_destroy(hz_field *f)
 {
-    if (f->used && f->last_use) (void)hipEventSynchronize(f->last_use);
+    for (const Ticket &t : f->uses) (void)ticket_sync(f->ctx, t);
     if (f->data) ctx_free(f->ctx, f->data, f->bytes);
-    if (f->last_use) (void)hipEventDestroy(f->last_use);
     delete f;
 }
 
-// Return a field's memory to the context pool; its last_use event orders any
+// Return a field's memory to the context pool; its last ticket orders any
 // reuse after the work that read it, so releasing never blocks the host.
 static void field_recycle(hz_field *f)
 {
     hz_ctx *c = f->ctx;
-    if (!f->used) {
+    if (f->uses.empty()) {
         field_destroy(f);
         return;
     }
     {
         std::lock_guard<std::mutex> g(c->pool_mu);
-        c->pool.push_back({f->data, (size_t)f->bytes, f->last_use});
+        c->pool.push_back({f->data, (size_t)f->bytes, std::move(f->uses)});
     }
     delete f;
 }
@@ -302,8 +359,7 @@ static void pool_trim(hz_ctx *c, size_t need)
     while (!c->pool.empty() && c->used.load() + need > c->budget) {
         hz_ctx::PoolBlock b = c->pool.back();
         c->pool.pop_back();
-        (void)hipEventSynchronize(b.ready);
-        (void)hipEventDestroy(b.ready);
+        for (const Ticket &t : b.uses) (void)ticket_sync(c, t);
         ctx_free(c, b.ptr, b.bytes);
     }
 }
@@ -336,11 +392,13 @@ static hipEvent_t prof_event_locked(hz_ctx *c)
 }
 
 // A start/stop pair for a group of launches, or nulls when profiling is off.
-static KTimer prof_timer(hz_ctx *c)
+static KTimer prof_timer(hz_ctx *c, const char *name)
 {
     KTimer t;
     if (!c->prof_on) return t;
     std::lock_guard<std::mutex> g(c->prof_mu);
+    if (!c->prof_only.empty() && std::find(c->prof_only.begin(), c->prof_only.end(), name) == c->prof_only.end())
+        return t;
     t.start = prof_event_locked(c);
     t.stop = prof_event_locked(c);
     if (!t.start || !t.stop) {
@@ -383,6 +441,27 @@ extern "C" hz_status hz_profile_enable(hz_ctx *c, int32_t enable)
     return HZ_OK;
 }
 
+extern "C" hz_status hz_profile_select(hz_ctx *c, const char *groups)
+{
+    if (!c) return fail(HZ_E_INVALID, "hz_profile_select: ctx is NULL");
+    static const char *const known[] = {"cell_list", "splat", "grad_pack", "raygen", "march", "serve_batch"};
+    std::vector<std::string> sel;
+    const std::string all = groups ? groups : "";
+    size_t a = 0;
+    while (a < all.size()) {
+        size_t b = all.find(',', a);
+        if (b == std::string::npos) b = all.size();
+        const std::string name = all.substr(a, b - a);
+        if (std::find(std::begin(known), std::end(known), name) == std::end(known))
+            return fail(HZ_E_INVALID, "hz_profile_select: unknown group '%s'", name.c_str());
+        sel.push_back(name);
+        a = b + 1;
+    }
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    c->prof_only = std::move(sel);
+    return HZ_OK;
+}
+
 extern "C" hz_status hz_profile_read(hz_ctx *c, const char *kernel, double *total_ms, int64_t *launches,
                                      int32_t reset)
 {
@@ -420,10 +499,11 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
                        &c->hits, &c->bins, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
-        if (p.used && p.done) (void)hipEventSynchronize(p.done);
+        (void)ticket_sync(c, p.last);
         if (p.host) (void)hipHostFree(p.host);
-        if (p.done) (void)hipEventDestroy(p.done);
     }
+    for (hipEvent_t e : c->tickets)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -493,21 +573,38 @@ static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale
     f->store_scale = scale;
     f->bytes = field_bytes(g, dt);
     {
-        // reuse a released block of the same size, ordered after its last use
+        // Reuse a released block of the same size, ordered after its last uses
+        // (which stay with the field until its producer has run).  A block
+        // still in use on another stream is taken only when the budget has no
+        // room for a new one, so that frames on two streams can overlap.
         std::lock_guard<std::mutex> lk(c->pool_mu);
-        for (size_t i = 0; i < c->pool.size(); ++i)
-            if (c->pool[i].bytes == f->bytes) {
-                f->data = c->pool[i].ptr;
-                f->last_use = c->pool[i].ready;
-                c->pool.erase(c->pool.begin() + (long)i);
-                break;
-            }
+        long pick = -1;
+        bool busy = false;
+        for (size_t i = 0; i < c->pool.size() && pick < 0; ++i) {
+            if (c->pool[i].bytes != f->bytes) continue;
+            bool idle = true;
+            for (const Ticket &t : c->pool[i].uses) idle = idle && (t.stream == s || ticket_done(c, t));
+            if (idle) pick = (long)i;
+            busy = busy || !idle;
+        }
+        if (pick < 0 && busy) {
+            const bool room = c->used.load() + f->bytes <= c->budget;
+            for (size_t i = 0; i < c->pool.size() && pick < 0 && !room; ++i)
+                if (c->pool[i].bytes == f->bytes) pick = (long)i;
+        }
+        if (pick >= 0) {
+            f->data = c->pool[(size_t)pick].ptr;
+            f->uses = std::move(c->pool[(size_t)pick].uses);
+            c->pool.erase(c->pool.begin() + pick);
+        }
     }
     if (f->data) {
-        hipError_t e = hipStreamWaitEvent(s, f->last_use, 0);
-        if (e != hipSuccess) {
-            field_destroy(f);
-            return hip_fail(e, "hipStreamWaitEvent");
+        for (const Ticket &t : f->uses) {
+            hz_status st = ticket_wait(c, t, s);
+            if (st != HZ_OK) {
+                field_destroy(f);
+                return st;
+            }
         }
         *out = f;
         return HZ_OK;
@@ -518,22 +615,39 @@ static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale
         delete f;
         return st;
     }
-    hipError_t e = hipEventCreateWithFlags(&f->last_use, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        ctx_free(c, f->data, f->bytes);
-        delete f;
-        return hip_fail(e, "hipEventCreate");
-    }
     *out = f;
     return HZ_OK;
 }
 
-static hz_status field_mark_used(hz_field *f, hipStream_t s)
+// The call with ticket t wrote the field; it ran after every earlier use.
+static void field_mark_made(hz_field *f, const Ticket &t)
 {
     std::lock_guard<std::mutex> g(f->mu);
-    HZ_HIP(hipEventRecord(f->last_use, s), "hipEventRecord");
-    f->used = true;
-    return HZ_OK;
+    f->made = t;
+    f->uses.assign(1, t);
+}
+
+// The call with ticket t read the field.
+static void field_mark_used(hz_field *f, const Ticket &t)
+{
+    std::lock_guard<std::mutex> g(f->mu);
+    for (Ticket &u : f->uses)
+        if (u.stream == t.stream) {
+            u = t;
+            return;
+        }
+    f->uses.push_back(t);
+}
+
+// Order a read of the field on `s` after the call that wrote it.
+static hz_status field_order_read(hz_ctx *c, hz_field *f, hipStream_t s)
+{
+    Ticket m;
+    {
+        std::lock_guard<std::mutex> g(f->mu);
+        m = f->made;
+    }
+    return ticket_wait(c, m, s);
 }
 
 static void register_field(hz_ctx *c, hz_field *f)
@@ -551,7 +665,7 @@ static hz_status pack_field(hz_ctx *c, const float *dn, const hz_grid *g, hz_fie
     int32_t res[3] = {g->res[0], g->res[1], g->res[2]};
     float inv_sp[3];
     for (int a = 0; a < 3; ++a) inv_sp[a] = (float)((double)g->res[a] / (g->hi[a] - g->lo[a]));
-    const KTimer t = prof_timer(c);
+    const KTimer t = prof_timer(c, "grad_pack");
     HZ_HIP(launch_grad_pack((int)f->dtype, dn, res, inv_sp, f->store_scale, f->data, s, t), "grad/pack launch");
     prof_commit(c, "grad_pack", t);
     return HZ_OK;
@@ -627,13 +741,13 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
     if (st != HZ_OK) return st;
 
-    const KTimer t0 = prof_timer(c);
+    const KTimer t0 = prof_timer(c, "cell_list");
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr, (uint32_t *)c->slots.ptr,
                                     (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s, t0);
     prof_commit(c, "cell_list", t0);
     if (e == hipSuccess) {
-        const KTimer t1 = prof_timer(c);
+        const KTimer t1 = prof_timer(c, "splat");
         if (scatter)
             e = launch_splat_scatter(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr,
                                      (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, s, t1);
@@ -651,8 +765,14 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         field_destroy(f);
         return st;
     }
-    for (int i = 0; i < 8; ++i) scratch_release(*bufs[i], s);
-    field_mark_used(f, s);
+    Ticket done;
+    st = ticket_issue(c, s, &done);
+    if (st != HZ_OK) {
+        field_destroy(f);
+        return st;
+    }
+    for (int i = 0; i < 8; ++i) bufs[i]->last = done;
+    field_mark_made(f, done);
     register_field(c, f);
     *out = f;
     return HZ_OK;
@@ -673,11 +793,13 @@ extern "C" hz_status hz_index_field_from_grid(hz_ctx *c, const float *dn, const 
     st = new_field(c, g, dtype, store_scale, s, &f);
     if (st != HZ_OK) return st;
     st = pack_field(c, dn, g, f, s);
+    Ticket done;
+    if (st == HZ_OK) st = ticket_issue(c, s, &done);
     if (st != HZ_OK) {
         field_destroy(f);
         return st;
     }
-    field_mark_used(f, s);
+    field_mark_made(f, done);
     register_field(c, f);
     *out = f;
     return HZ_OK;
@@ -692,8 +814,13 @@ extern "C" hz_status hz_field_read(hz_ctx *c, const hz_field *fc, float *dn, flo
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t nv = (int64_t)f->grid.res[0] * f->grid.res[1] * f->grid.res[2];
+    hz_status st = field_order_read(c, f, s);
+    if (st != HZ_OK) return st;
     HZ_HIP(launch_field_unpack((int)f->dtype, f->data, nv, 1.0f / f->store_scale, dn, gx, gy, gz, s), "unpack launch");
-    return field_mark_used(f, s);
+    Ticket done;
+    st = ticket_issue(c, s, &done);
+    if (st == HZ_OK) field_mark_used(f, done);
+    return st;
 }
 
 extern "C" hz_status hz_field_info(const hz_field *f, hz_grid *grid, hz_dtype *dtype, float *store_scale,
@@ -839,13 +966,14 @@ void make_trace_step(const hz_step &st, const hz_grid &g, TraceStep *S)
 
 }  // namespace haze
 
-// Copy `bytes` from host to device through a pinned staging slot.
-static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes, hipStream_t s)
+// Copy `bytes` from host to device through a pinned staging slot; the caller
+// stamps *slot with its call's ticket.
+static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes, hipStream_t s, PinnedSlot **slot)
 {
     PinnedSlot &p = c->pinned[c->pinned_next];
     c->pinned_next = (c->pinned_next + 1) % c->pinned.size();
-    if (!p.done) HZ_HIP(hipEventCreateWithFlags(&p.done, hipEventDisableTiming), "hipEventCreate");
-    if (p.used) HZ_HIP(hipEventSynchronize(p.done), "hipEventSynchronize");
+    hz_status st = ticket_sync(c, p.last);
+    if (st != HZ_OK) return st;
     if (p.cap < bytes) {
         if (p.host) (void)hipHostFree(p.host);
         p.host = nullptr;
@@ -855,8 +983,7 @@ static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes
     }
     std::memcpy(p.host, src, bytes);
     HZ_HIP(hipMemcpyAsync(dst, p.host, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-    HZ_HIP(hipEventRecord(p.done, s), "hipEventRecord");
-    p.used = true;
+    *slot = &p;
     return HZ_OK;
 }
 
@@ -993,8 +1120,10 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->bins, (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->counters, kCounterBytes, s);
+    if (st == HZ_OK) st = field_order_read(c, f, s);
     if (st != HZ_OK) return st;
-    st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s);
+    PinnedSlot *staging = nullptr;
+    st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s, &staging);
     if (st != HZ_OK) return st;
     L.jobs = (const TraceJob *)c->jobs.ptr;
     L.quads = quad_bytes ? (const SceneQuad *)((unsigned char *)c->jobs.ptr + job_bytes) : nullptr;
@@ -1011,17 +1140,19 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
     blocks64 = std::max<int64_t>(1, blocks64);
     const int blocks = (int)blocks64;
-    const KTimer t0 = prof_timer(c);
+    const KTimer t0 = prof_timer(c, "raygen");
     HZ_HIP(launch_raygen(L, s, t0), "raygen launch");
     prof_commit(c, "raygen", t0);
-    const KTimer t1 = prof_timer(c);
+    const KTimer t1 = prof_timer(c, "march");
     HZ_HIP(launch_march(dt, L, blocks, s, t1), "march launch");
     prof_commit(c, "march", t1);
-    scratch_release(c->jobs, s);
-    scratch_release(c->hits, s);
-    scratch_release(c->bins, s);
-    scratch_release(c->counters, s);
-    return field_mark_used(f, s);
+    Ticket done;
+    st = ticket_issue(c, s, &done);
+    if (st != HZ_OK) return st;
+    for (Scratch *b : {&c->jobs, &c->hits, &c->bins, &c->counters}) b->last = done;
+    staging->last = done;
+    field_mark_used(f, done);
+    return HZ_OK;
 }
 
 extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
@@ -1050,9 +1181,11 @@ hz_dtype field_dtype(const hz_field *f) { return f->dtype; }
 float field_scale(const hz_field *f) { return f->store_scale; }
 const void *field_data(const hz_field *f) { return f->data; }
 hz_ctx *field_ctx(const hz_field *f) { return f->ctx; }
-hz_status field_use(hz_field *f, hipStream_t s) { return field_mark_used(f, s); }
+hz_status ctx_ticket(hz_ctx *c, hipStream_t s, Ticket *out) { return ticket_issue(c, s, out); }
+void field_use(hz_field *f, const Ticket &t) { field_mark_used(f, t); }
+hz_status field_ready(hz_field *f, hipStream_t s) { return field_order_read(f->ctx, f, s); }
 int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
-KTimer profile_timer(hz_ctx *c) { return prof_timer(c); }
+KTimer profile_timer(hz_ctx *c, const char *name) { return prof_timer(c, name); }
 void profile_commit(hz_ctx *c, const char *name, const KTimer &t) { prof_commit(c, name, t); }
 hz_status set_error(hz_status s, const char *msg) { return fail(s, "%s", msg); }
 }  // namespace haze

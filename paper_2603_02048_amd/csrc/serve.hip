@@ -169,6 +169,10 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
             return set_error(HZ_E_NOMEM, "serve: hipHostMalloc failed");
         sl.pinned_cap = job_bytes;
     }
+    for (Request *r : batch) {
+        hz_status st = field_ready(r->field, sl.stream);
+        if (st != HZ_OK) return st;
+    }
     // the slot is idle, so its previous copy out of `pinned` has completed
     std::memcpy(sl.pinned, jobs.data(), job_bytes);
     if (hipMemcpyAsync(sl.jobs, sl.pinned, job_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
@@ -190,14 +194,17 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.refill_min = 16;
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
-    const KTimer t = profile_timer(S->ctx);
+    const KTimer t = profile_timer(S->ctx, "serve_batch");
     if (launch_raygen(L, sl.stream, KTimer{t.start, nullptr}) != hipSuccess ||
         launch_march(dt, L, blocks, sl.stream, KTimer{nullptr, t.stop}) != hipSuccess)
         return set_error(HZ_E_DEVICE, "serve: trace launch failed");
     profile_commit(S->ctx, "serve_batch", t);
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
+    Ticket done;
+    hz_status st = ctx_ticket(S->ctx, sl.stream, &done);
+    if (st != HZ_OK) return st;
     for (Request *r : batch) {
-        field_use(r->field, sl.stream);
+        field_use(r->field, done);
         r->state = REQ_RUNNING;
     }
     sl.reqs = batch;

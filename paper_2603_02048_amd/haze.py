@@ -74,7 +74,7 @@ class hz_scene(C.Structure):
 
 
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
-           "hz_profile_read", "hz_membench", "hz_splat_index_field",
+           "hz_profile_select", "hz_profile_read", "hz_membench", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_trace_scene",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
@@ -99,6 +99,7 @@ def lib():
         L.hz_membench.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(C.c_double), P]
         L.hz_membench.restype = S
         L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
+        L.hz_profile_select.argtypes, L.hz_profile_select.restype = [P, C.c_char_p], S
         L.hz_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.hz_profile_read.restype = S
         L.hz_splat_index_field.argtypes = [P, C.POINTER(hz_particles), C.POINTER(hz_grid),
@@ -261,6 +262,13 @@ class Context:
 
     def profile_enable(self, enable: bool = True):
         _check(lib().hz_profile_enable(C.c_void_p(self.handle), 1 if enable else 0), "profile_enable")
+
+    def profile_select(self, groups=None):
+        """Time only the named groups (a list or comma-separated string); None: all."""
+        if groups is not None and not isinstance(groups, str):
+            groups = ",".join(groups)
+        _check(lib().hz_profile_select(C.c_void_p(self.handle), groups.encode() if groups else None),
+               "profile_select")
 
     def profile_read(self, kernel: str, reset: bool = False) -> tuple:
         """(total milliseconds, launch count) of a kernel since the last reset."""
