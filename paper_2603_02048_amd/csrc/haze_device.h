@@ -131,6 +131,7 @@ struct TraceLaunch {
     uint32_t *hits;        // slots of the rays that enter the volume, sorted by length bin
     uint8_t *slot_bin;     // per slot: length bin of an entering ray, 255 otherwise
     uint32_t *counters;    // bin totals, placement cursors, march batch head (hit_counter)
+    uint32_t *counters_next;   // the other set, cleared here for the next launch
     float inv_len_bin;     // kRayBins / (box diagonal): chord length -> bin
     TraceGrid grid;
     TraceStep step;
@@ -149,12 +150,16 @@ struct TraceLaunch {
 // 2 places each ray in its bin's range of the hit list.  Counters sit
 // kCounterStride words (256 B) apart so that no two share a cache line:
 // bin totals [0, kRayBins), placement cursors [kRayBins, 2 kRayBins), and the
-// march's dynamic batch head at 2 kRayBins.
+// march's dynamic batch head at 2 kRayBins.  Counter memory holds two such
+// sets used by alternate launches: ray generation clears the set the next
+// launch will use, so no launch of its own clears counters (new memory is
+// cleared once by k_trace_init).
 constexpr int kRayBins = 32;
 constexpr int kCounterStride = 64;
 constexpr int kRaygenBlock = 256;
 constexpr int kMarchHead = 2 * kRayBins;
-constexpr size_t kCounterBytes = (size_t)(kMarchHead + 1) * kCounterStride * 4;
+constexpr size_t kCounterSetWords = (size_t)(kMarchHead + 1) * kCounterStride;
+constexpr size_t kCounterBytes = 2 * kCounterSetWords * 4;
 __host__ __device__ inline uint32_t *hit_counter(uint32_t *counters, int k) { return counters + k * kCounterStride; }
 
 // Field storage types (match hz_dtype).

@@ -23,9 +23,11 @@
 
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
-                            uint32_t *, uint32_t *, uint32_t *, uint32_t *, uint32_t *, float4 *, uint32_t *, bool,
-                            hipStream_t, const KTimer &);
+                            uint32_t *, uint32_t *, int64_t, uint32_t *, uint32_t *, uint32_t *, float4 *, void *,
+                            bool, uint32_t *, bool, hipStream_t, const KTimer &);
 int32_t scan_tiles(int32_t ncells);
+size_t scan_scratch_bytes(int32_t ncells);
+bool scan_is_onepass(int32_t ncells);
 hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t, const KTimer &);
 hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const float4 *, const uint32_t *, float *,
                                 hipStream_t, const KTimer &);
@@ -34,7 +36,7 @@ int scatter_rows_limit();
 hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t,
                             const KTimer &);
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
-hipError_t launch_raygen(const TraceLaunch &, hipStream_t, const KTimer &);
+hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 int march_blocks_per_cu(int, int);
 }  // namespace haze
@@ -80,6 +82,7 @@ struct Scratch {
     void *ptr = nullptr;
     size_t cap = 0;
     Ticket last;
+    bool clean = false;   // holds what its kernels expect on entry (new memory: no)
 };
 
 struct PinnedSlot {
@@ -109,10 +112,14 @@ struct hz_ctx {
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
     std::mutex ledger_mu;
-    // splat scratch
+    // splat scratch; `count` is clean when all zero, `tiles` when the one-pass
+    // scan's ticket counter equals scan_base and its tags are older
     Scratch cid, count, start, lrank, slots, sorted, dn, tiles;
-    // trace scratch
+    uint32_t scan_base = 0;
+    // trace scratch; `counters` holds two counter sets used alternately,
+    // counter_set the one the next launch uses
     Scratch jobs, hits, bins, counters;
+    int counter_set = 0;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
     hipEvent_t tickets[kTicketRing] = {};
@@ -283,6 +290,7 @@ static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_
         }
         size_t want = std::max<size_t>(bytes, 4096);
         want = (want + 4095) & ~(size_t)4095;
+        s.clean = false;
         st = ctx_alloc(c, &s.ptr, want);
         if (st != HZ_OK) return st;
         s.cap = want;
@@ -728,7 +736,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     Scratch *bufs[8] = {&c->cid, &c->count, &c->start, &c->lrank, &c->slots, &c->sorted, &c->dn, &c->tiles};
     const size_t sizes[8] = {4u * (size_t)n, 4u * (size_t)(ncells + 2), 4u * (size_t)(ncells + 1),
                              4u * (size_t)n, 4u * (size_t)n, 16u * (size_t)n, 4u * (size_t)nv,
-                             4u * (size_t)scan_tiles((int32_t)ncells)};
+                             scan_scratch_bytes((int32_t)ncells)};
     for (int i = 0; i < 8; ++i) {
         st = scratch_acquire(c, *bufs[i], sizes[i], s);
         if (st != HZ_OK) return st;
@@ -741,11 +749,25 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
     if (st != HZ_OK) return st;
 
+    // Histogram memory is cleared only when not known to be zero (new, or after
+    // a scatter-splat call, which leaves max |m| behind); the scan clears what
+    // it reads.  The one-pass scan's counter is reset when new, after a
+    // three-pass scan, or before its tickets would wrap.
+    const int32_t ntiles = scan_tiles((int32_t)ncells);
+    const int64_t clear_words = (c->count.clean && !scatter) ? 0 : (int64_t)(c->count.cap / 4);
+    const bool scan_reset = !c->tiles.clean || c->scan_base > 0xffffffffu - (uint32_t)ntiles - 1u;
+    c->count.clean = false;
+    c->tiles.clean = false;
     const KTimer t0 = prof_timer(c, "cell_list");
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
-                                    (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr, (uint32_t *)c->slots.ptr,
-                                    (float4 *)c->sorted.ptr, (uint32_t *)c->tiles.ptr, scatter, s, t0);
+                                    clear_words, (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr,
+                                    (uint32_t *)c->slots.ptr, (float4 *)c->sorted.ptr, c->tiles.ptr, scan_reset,
+                                    &c->scan_base, scatter, s, t0);
     prof_commit(c, "cell_list", t0);
+    if (e == hipSuccess) {
+        c->count.clean = !scatter;
+        c->tiles.clean = scan_is_onepass((int32_t)ncells);
+    }
     if (e == hipSuccess) {
         const KTimer t1 = prof_timer(c, "splat");
         if (scatter)
@@ -1128,7 +1150,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     L.jobs = (const TraceJob *)c->jobs.ptr;
     L.quads = quad_bytes ? (const SceneQuad *)((unsigned char *)c->jobs.ptr + job_bytes) : nullptr;
     L.hits = (uint32_t *)c->hits.ptr;
-    L.counters = (uint32_t *)c->counters.ptr;
+    L.counters = (uint32_t *)c->counters.ptr + (size_t)c->counter_set * kCounterSetWords;
+    L.counters_next = (uint32_t *)c->counters.ptr + (size_t)(1 - c->counter_set) * kCounterSetWords;
     L.slot_bin = (uint8_t *)c->bins.ptr;
     L.inv_len_bin = length_bin_scale(f->grid);
     const int dt = (int)f->dtype;
@@ -1140,12 +1163,18 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
     blocks64 = std::max<int64_t>(1, blocks64);
     const int blocks = (int)blocks64;
+    // this launch's counter set was cleared by the previous launch's ray
+    // generation; new memory, or a set after a failed call, needs clearing
+    const bool clear = !c->counters.clean;
+    c->counters.clean = false;
     const KTimer t0 = prof_timer(c, "raygen");
-    HZ_HIP(launch_raygen(L, s, t0), "raygen launch");
+    HZ_HIP(launch_raygen(L, clear, s, t0), "raygen launch");
     prof_commit(c, "raygen", t0);
     const KTimer t1 = prof_timer(c, "march");
     HZ_HIP(launch_march(dt, L, blocks, s, t1), "march launch");
     prof_commit(c, "march", t1);
+    c->counter_set = 1 - c->counter_set;
+    c->counters.clean = true;
     Ticket done;
     st = ticket_issue(c, s, &done);
     if (st != HZ_OK) return st;

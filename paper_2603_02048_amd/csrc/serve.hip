@@ -27,7 +27,7 @@
 #include <vector>
 
 namespace haze {
-hipError_t launch_raygen(const TraceLaunch &, hipStream_t, const KTimer &);
+hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 hz_status check_step(const hz_step *st, const char *fn);
 hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
@@ -63,7 +63,9 @@ struct Slot {
     size_t pinned_cap = 0;
     void *hits = nullptr;       // u32 per queue slot
     void *bins = nullptr;       // u8 per queue slot (length bins of the ray sort)
-    void *counters = nullptr;
+    void *counters = nullptr;      // two counter sets, used alternately
+    int counter_set = 0;
+    bool counters_clean = false;   // the set in turn is zero
     size_t scratch_bytes = 0;
 };
 
@@ -186,7 +188,8 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.nslots = slot;
     L.ray_ids = nullptr;
     L.hits = (uint32_t *)sl.hits;
-    L.counters = (uint32_t *)sl.counters;
+    L.counters = (uint32_t *)sl.counters + (size_t)sl.counter_set * kCounterSetWords;
+    L.counters_next = (uint32_t *)sl.counters + (size_t)(1 - sl.counter_set) * kCounterSetWords;
     L.slot_bin = (uint8_t *)sl.bins;
     L.inv_len_bin = length_bin_scale(field_grid(head->field));
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
@@ -195,9 +198,13 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
     const KTimer t = profile_timer(S->ctx, "serve_batch");
-    if (launch_raygen(L, sl.stream, KTimer{t.start, nullptr}) != hipSuccess ||
+    const bool clear = !sl.counters_clean;
+    sl.counters_clean = false;
+    if (launch_raygen(L, clear, sl.stream, KTimer{t.start, nullptr}) != hipSuccess ||
         launch_march(dt, L, blocks, sl.stream, KTimer{nullptr, t.stop}) != hipSuccess)
         return set_error(HZ_E_DEVICE, "serve: trace launch failed");
+    sl.counter_set = 1 - sl.counter_set;
+    sl.counters_clean = true;
     profile_commit(S->ctx, "serve_batch", t);
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
     Ticket done;

@@ -89,12 +89,16 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
     }
 }
 
-// Exclusive scan of count[0..n) into start[0..n] (start[n] = total) in three
-// passes over tiles of SCAN_TILE cells: tile sums, scan of the tile sums (one
-// workgroup), then each tile rescanned with its offset.
+// Exclusive scan of count[0..n) into start[0..n] (start[n] = total) over
+// tiles of SCAN_TILE cells, clearing the counts as it reads them (so the
+// histogram starts the next call at zero).  Up to SCAN_ONEPASS_TILES tiles
+// it is one launch (k_scan_onepass); beyond, three passes: tile sums, scan of
+// the tile sums (one workgroup), then each tile rescanned with its offset.
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
+constexpr int SCAN_ONEPASS_TILES = 1024;
+constexpr size_t SCAN_TAG_OFFSET = 256;   // bytes: the ticket counter, then the tile tags
 
 // Inclusive scan of one value per thread across a 256-thread workgroup.
 __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *wave_tot)
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(uint32_t *__res
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *__restrict__ count, int32_t n,
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(uint32_t *__restrict__ count, int32_t n,
                                                              const uint32_t *__restrict__ tile_off,
                                                              uint32_t *__restrict__ start)
 {
@@ -160,12 +164,77 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t *__r
         v[k] = base + k < n ? count[base + k] : 0u;
         s += v[k];
     }
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k)
+        if (base + k < n) count[base + k] = 0u;
     uint32_t run = tile_off[blockIdx.x] + block_scan_incl(s, wt) - s;
 #pragma unroll
     for (int k = 0; k < SCAN_PER_THREAD; ++k) {
         if (base + k < n) start[base + k] = run;
         run += v[k];
     }
+}
+
+// One-launch scan.  Workgroups take tiles in the order they start, from a
+// running ticket counter (tile = ticket - base, where base is the counter's
+// value at launch), publish their tile's sum tagged with their ticket, and add
+// the sums of all lower tiles.  Each lower tile belongs to a workgroup that
+// took its ticket earlier and is therefore already running, and it waits only
+// on tiles lower still, so every wait ends.  (The bound on the spin is a
+// guard, never reached.)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_onepass(uint32_t *__restrict__ count, int32_t n,
+                                                               int32_t ntiles, uint32_t *__restrict__ ticket_ctr,
+                                                               uint64_t *__restrict__ tags, uint32_t base,
+                                                               uint32_t *__restrict__ start)
+{
+    __shared__ uint32_t wt[4];
+    __shared__ uint32_t sh_ticket;
+    __shared__ uint32_t sh_lower[4];
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(ticket_ctr, 1u);
+    __syncthreads();
+    const uint32_t ticket = sh_ticket;
+    const int32_t tile = (int32_t)(ticket - base);
+    const int64_t b0 = (int64_t)tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        v[k] = b0 + k < n ? count[b0 + k] : 0u;
+        s += v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k)
+        if (b0 + k < n) count[b0 + k] = 0u;
+    const uint32_t incl = block_scan_incl(s, wt);
+    // tag = ticket + 1: cleared memory (tag 0) never passes for a sum.  The
+    // tag and the sum travel in one 64-bit word, so relaxed device-scope
+    // atomics suffice (no fences, which would write back and invalidate L2).
+    if (threadIdx.x == SCAN_THREADS - 1)
+        __hip_atomic_store(&tags[tile], ((uint64_t)(ticket + 1u) << 32) | incl, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t lower = 0;
+    for (int32_t t = (int32_t)threadIdx.x; t < tile; t += SCAN_THREADS) {
+        const uint32_t want = base + (uint32_t)t + 1u;
+        uint64_t w = 0;
+        for (uint32_t spin = 0; spin < (1u << 26); ++spin) {
+            w = __hip_atomic_load(&tags[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(w >> 32) == want) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        lower += (uint32_t)w;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lower += (uint32_t)__shfl_xor((int)lower, off);
+    if ((threadIdx.x & 63) == 0) sh_lower[threadIdx.x >> 6] = lower;
+    __syncthreads();
+    const uint32_t offset = sh_lower[0] + sh_lower[1] + sh_lower[2] + sh_lower[3];
+    uint32_t run = offset + incl - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (b0 + k < n) start[b0 + k] = run;
+        run += v[k];
+    }
+    if (tile == ntiles - 1 && threadIdx.x == SCAN_THREADS - 1) start[n] = run;
 }
 
 // Every binned particle takes the slot of its cell given by its arrival rank.
@@ -569,25 +638,55 @@ static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t -
 
 int32_t scan_tiles(int32_t ncells) { return (ncells + SCAN_TILE - 1) / SCAN_TILE; }
 
+size_t scan_scratch_bytes(int32_t ncells) { return SCAN_TAG_OFFSET + 8u * (size_t)scan_tiles(ncells); }
+
+bool scan_is_onepass(int32_t ncells) { return scan_tiles(ncells) <= SCAN_ONEPASS_TILES; }
+
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
-                            const CellGrid &cg, uint32_t *cid, uint32_t *count, uint32_t *start, uint32_t *lrank,
-                            uint32_t *slots, float4 *sorted, uint32_t *tile_sum, bool want_mmax, hipStream_t s,
-                            const KTimer &t)
+                            const CellGrid &cg, uint32_t *cid, uint32_t *count, int64_t count_clear_words,
+                            uint32_t *start, uint32_t *lrank, uint32_t *slots, float4 *sorted, void *scan,
+                            bool scan_reset, uint32_t *scan_base, bool want_mmax, hipStream_t s, const KTimer &t)
 {
-    // count[ncells + 1] holds max |m| (scatter splat only); both start at zero
-    hipExtLaunchKernelGGL(k_fill_u32, dim3(blocks_for(cg.ncells + 2, 256)), dim3(256), 0, s, t.start, nullptr, 0,
-                          count, 0u, (int64_t)cg.ncells + 2);
+    // The counts must start at zero; each scan leaves them so.  count[ncells+1]
+    // holds max |m| (scatter splat only), which the caller clears through
+    // count_clear_words.  The scan scratch starts with the one-pass scan's
+    // ticket counter, then the tile tags (both cleared by scan_reset).
+    const int32_t ntiles = scan_tiles(cg.ncells);
+    const bool onepass = ntiles <= SCAN_ONEPASS_TILES;
+    bool first = true;
+    if (count_clear_words > 0) {
+        hipExtLaunchKernelGGL(k_fill_u32, dim3(blocks_for(count_clear_words, 256)), dim3(256), 0, s, t.start, nullptr,
+                              0, count, 0u, count_clear_words);
+        first = false;
+    }
+    if (onepass && scan_reset) {
+        const int64_t words = (int64_t)(scan_scratch_bytes(cg.ncells) / 4);
+        hipExtLaunchKernelGGL(k_fill_u32, dim3(blocks_for(words, 256)), dim3(256), 0, s, first ? t.start : nullptr,
+                              nullptr, 0, (uint32_t *)scan, 0u, words);
+        first = false;
+        *scan_base = 0;
+    }
     if (want_mmax)
-        hipLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
-                           lrank, count, count + cg.ncells + 1);
+        hipExtLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                              first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
+                              count + cg.ncells + 1);
     else
-        hipLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, z, m, n, cg, cid,
-                           lrank, count, count + cg.ncells + 1);
-    const int32_t ntiles = (cg.ncells + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles, start + cg.ncells);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, tile_sum,
-                       start);
+        hipExtLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+                              first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
+                              count + cg.ncells + 1);
+    if (onepass) {
+        hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, ntiles,
+                           (uint32_t *)scan, (uint64_t *)((char *)scan + SCAN_TAG_OFFSET), *scan_base, start);
+        *scan_base += (uint32_t)ntiles;
+    } else {
+        uint32_t *tile_sum = (uint32_t *)scan;
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells,
+                           tile_sum);
+        hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles,
+                           start + cg.ncells);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells,
+                           tile_sum, start);
+    }
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots);
     hipExtLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, nullptr, t.stop, 0, cid, start,
                           slots, n, x, y, z, m, sorted);

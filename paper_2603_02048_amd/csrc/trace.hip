@@ -327,6 +327,9 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
             if (L.flat.surface) L.flat.surface[slot] = 255u;
         }
     }
+    // the next launch's counter set (this launch's march uses the other one)
+    static_assert(kMarchHead < kRaygenBlock, "one workgroup clears a counter set");
+    if (blockIdx.x == 0 && threadIdx.x <= kMarchHead) *hit_counter(L.counters_next, threadIdx.x) = 0u;
     // pass 1 of the length sort: remember the bin, count the bins of the
     // workgroup (wave ballots), one atomic per non-empty bin
     if (!enters) bin = 255;
@@ -695,15 +698,17 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
 // host launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_raygen(const TraceLaunch &L, hipStream_t s, const KTimer &t)
+// Ray generation for L.nslots > 0 slots; `clear_counters` when the set
+// L.counters was not cleared by the previous launch's ray generation (new
+// memory, or after a failed launch).
+hipError_t launch_raygen(const TraceLaunch &L, bool clear_counters, hipStream_t s, const KTimer &t)
 {
-    hipExtLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, t.start, L.nslots > 0 ? nullptr : t.stop, 0,
-                          L.counters);
-    if (L.nslots > 0) {
-        const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
-        hipLaunchKernelGGL(k_raygen, g, dim3(kRaygenBlock), 0, s, L);
-        hipExtLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, nullptr, t.stop, 0, L);
-    }
+    if (L.nslots <= 0) return hipSuccess;
+    if (clear_counters)
+        hipExtLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, t.start, nullptr, 0, L.counters);
+    const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
+    hipExtLaunchKernelGGL(k_raygen, g, dim3(kRaygenBlock), 0, s, clear_counters ? nullptr : t.start, nullptr, 0, L);
+    hipExtLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, nullptr, t.stop, 0, L);
     return hipGetLastError();
 }
 

@@ -113,6 +113,33 @@ def test_splat_particles_outside_grid(ctx, haze):
     field.release()
 
 
+def test_splat_cell_scan_paths(ctx, haze):
+    # The cell histogram is scanned in one launch up to 1024 tiles of 2048
+    # cells and in three passes beyond; the histogram and the one-pass scan's
+    # counter carry state from call to call.  Alternate the two paths (a
+    # support far below the voxel size gives ~9e6 cells), with the scatter
+    # splat in between, in one context.
+    small = W.make_small(seed=4, n=6000)
+    fine = W.make_small(seed=5, n=20000, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), res=(64, 64, 64), h=0.005)
+    refs = {}
+    for wl, method in ((small, "gather"), (fine, "gather"), (small, "gather"), (small, "scatter"),
+                       (small, "gather"), (fine, "gather"), (fine, "gather")):
+        ctx.tune("splat.method", SPLAT_METHODS[method])
+        try:
+            if wl.name + str(wl.h) not in refs:
+                refs[wl.name + str(wl.h)] = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h).arrays
+            ref = refs[wl.name + str(wl.h)]
+            print(f"case scan paths: h={wl.h} res={tuple(wl.grid.res)} {method}", flush=True)
+            parts = haze.upload_particles(wl.particles)
+            f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+            dn, gx, gy, gz = _field_np(ctx, f)
+            assert np.count_nonzero(ref[0]) > 1000
+            assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing, f"scan paths h={wl.h} {method}")
+            f.release()
+        finally:
+            ctx.tune("splat.method", 0)
+
+
 @pytest.mark.parametrize("kgd", [1.0, 200.0])
 @pytest.mark.parametrize("mode", ["adaptive", "uniform", "adaptive_fine"])
 def test_trace_parity_small(ctx, haze, kgd, mode):

@@ -100,8 +100,9 @@ def test_serve_budget_admission_and_errors(haze):
     used_with_field, _ = probe.memory()
     probe.close()
     max_batch = 256 * 128
-    # slot scratch: hit list (4 B) and length bins (1 B) per queue slot, 33 counters 256 B apart
-    budget = used_with_field + 5 * max_batch + 33 * 256 + 64 * 1024 + int(1.5 * per_req)
+    # slot scratch: hit list (4 B) and length bins (1 B) per queue slot, two
+    # sets of 65 counters 256 B apart
+    budget = used_with_field + 5 * max_batch + 2 * 65 * 256 + 64 * 1024 + int(1.5 * per_req)
     ctx = haze.Context(0, budget_bytes=budget)
     try:
         f = ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
