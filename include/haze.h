@@ -148,7 +148,8 @@ typedef struct {
     const float *x, *y, *z, *m;
 } hz_particles;
 
-/* Regular grid over the box [lo, hi] with res[0] x res[1] x res[2] voxels. */
+/* Regular grid over the box [lo, hi] with res[0] x res[1] x res[2] voxels:
+ * 2 <= res[a] <= 65535 on each axis and fewer than 2^31 voxels in all. */
 typedef struct {
     double lo[3], hi[3];
     int32_t res[3];

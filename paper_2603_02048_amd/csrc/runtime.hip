@@ -552,7 +552,8 @@ static hz_status check_grid(const hz_grid *g, const char *fn)
     for (int a = 0; a < 3; ++a) {
         if (!(std::isfinite(g->lo[a]) && std::isfinite(g->hi[a]) && g->hi[a] > g->lo[a]))
             return fail(HZ_E_INVALID, "%s: grid axis %d needs finite lo < hi", fn, a);
-        if (g->res[a] < 2) return fail(HZ_E_INVALID, "%s: grid res[%d] = %d < 2", fn, a, g->res[a]);
+        if (g->res[a] < 2 || g->res[a] > 65535)
+            return fail(HZ_E_INVALID, "%s: grid res[%d] = %d outside [2, 65535]", fn, a, g->res[a]);
         nv *= g->res[a];
         if (nv > INT32_MAX) return fail(HZ_E_INVALID, "%s: more than 2^31 - 1 voxels", fn);
     }

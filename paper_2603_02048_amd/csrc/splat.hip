@@ -265,9 +265,19 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
     const uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
     const uint32_t b = start[c], e = start[c + 1];
+    const float4 rec = make_float4(x[i], y[i], z[i], m[i]);
+    // Eight slots per round with all eight loads in flight before any compare
+    // (the loop is latency-bound); indices are clamped into the cell, which
+    // holds at least particle i, and a clamped repeat is not counted.
     uint32_t rank = 0;
-    for (uint32_t t = b; t < e; ++t) rank += slots[t] < (uint32_t)i ? 1u : 0u;
-    sorted[b + rank] = make_float4(x[i], y[i], z[i], m[i]);
+    for (uint32_t t = b; t < e; t += 8) {
+        uint32_t sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[u] = slots[min(t + (uint32_t)u, e - 1u)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rank += (t + (uint32_t)u < e && sv[u] < (uint32_t)i) ? 1u : 0u;
+    }
+    sorted[b + rank] = rec;
 }
 
 // Adds one candidate particle's M4-spline terms to the lane's column of voxels.
@@ -552,18 +562,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+// A workgroup covers 64 x 4 voxels of one z-slice: grid (ceil(rx/64),
+// ceil(ry/4), rz), so no index division.
 template <int DT>
 __global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t rx, int32_t ry, int32_t rz,
                                                    float ix, float iy, float iz, float scale, void *__restrict__ out)
 {
+    const int32_t i = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
+    const int32_t j = (int32_t)blockIdx.y * 4 + (int32_t)(threadIdx.x >> 6);
+    const int32_t k = (int32_t)blockIdx.z;
+    if (i >= rx || j >= ry) return;
     // voxel counts are below 2^31 (checked on the host): 32-bit index math
-    const int32_t v = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if ((int64_t)v >= (int64_t)rx * ry * rz) return;
-    const int32_t ij = v / rx;
-    const int32_t i = v - ij * rx;
-    const int32_t k = ij / ry;
-    const int32_t j = ij - k * ry;
     const int32_t sy = rx, sz = rx * ry;
+    const int32_t v = (k * ry + j) * rx + i;
     const float c = dn[v];
     float g[3];
     {
@@ -707,8 +718,7 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
 hipError_t launch_grad_pack(int dtype, const float *dn, const int32_t res[3], const float inv_sp[3], float scale,
                             void *out, hipStream_t s, const KTimer &t)
 {
-    const int64_t nv = (int64_t)res[0] * res[1] * res[2];
-    const dim3 g(blocks_for(nv, 256)), b(256);
+    const dim3 g((unsigned)((res[0] + 63) / 64), (unsigned)((res[1] + 3) / 4), (unsigned)res[2]), b(256);
     if (dtype == DT_F32)
         hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
                               inv_sp[0], inv_sp[1], inv_sp[2], scale, out);

@@ -269,6 +269,17 @@ def test_trace_edge_cases(ctx, haze):
     field.release()
 
 
+def test_grid_limits_rejected(ctx, haze):
+    # each axis holds 2 to 65535 voxels; nothing is launched for a bad grid
+    wl = W.make_small(seed=6, n=500)
+    parts = haze.upload_particles(wl.particles)
+    for res in ((1, 8, 8), (8, 65536, 2), (65536, 2, 2)):
+        bad = W.make_grid(wl.grid.lo, wl.grid.hi, res)
+        with pytest.raises(haze.HazeError) as e:
+            ctx.splat_index_field(parts, bad, wl.k_gd, wl.h)
+        assert e.value.status == haze.E_INVALID and "65535" in str(e.value)
+
+
 def test_field_from_grid_linear_and_catenary(ctx, haze):
     # a linear delta-n grid: the GPU gradient is exact up to rounding and the
     # rays follow the oracle's (grid-exact) catenary replica
