@@ -292,13 +292,14 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
             const float dz = cz[v] - q.z;
             const float r2 = fmaf(dz, dz, dxy);
             if (r2 < P.support2) {
-                // M4 spline: 1 - 1.5q^2 + 0.75q^3 (q<1), 0.25(2-q)^3 (1<=q<2),
-                // written 0.25 a^3 - b^3 with a = 2 - q (> 0 here) and
-                // b = max(1 - q, 0)
-                const float a = fmaf(-__builtin_amdgcn_sqrtf(r2), P.inv_h, 2.0f);
-                const float b = fmaxf(a - 1.0f, 0.0f);
-                const float w = 0.25f * (a * a * a) - b * b * b;
-                acc[v] = fmaf(q.w, w, acc[v]);
+                // M4 spline times 4: 4 - 6q^2 + 3q^3 (q < 1), (2 - q)^3 (1 <= q < 2).
+                // With u = 1 - q (in (-1, 1] here) both pieces are
+                // 1 + 3u + 3u^2 + c u^3, c = -3 for u > 0 and 1 otherwise: one
+                // select and three FMAs (the factor 1/4 is in the final scale)
+                const float u = fmaf(-__builtin_amdgcn_sqrtf(r2), P.inv_h, 1.0f);
+                const float c3 = u > 0.0f ? -3.0f : 1.0f;
+                const float w4 = fmaf(fmaf(fmaf(c3, u, 3.0f), u, 3.0f), u, 1.0f);
+                acc[v] = fmaf(q.w, w4, acc[v]);
             }
         }
     }
@@ -387,7 +388,8 @@ __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__
     if (vx < P.res[0] && vy < P.res[1]) {
 #pragma unroll
         for (int v = 0; v < SPLAT_BZ; ++v)
-            if (vz0 + v < P.res[2]) dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = acc[v] * P.scale;
+            if (vz0 + v < P.res[2])
+                dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = acc[v] * (0.25f * P.scale);
     }
 }
 
