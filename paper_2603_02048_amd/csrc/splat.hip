@@ -305,24 +305,30 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
     }
 }
 
-// One wave per brick of 8 x 8 x 4 voxels: lane (lane & 7, lane >> 3) owns the
-// column of four voxels along z.  All lanes walk the same candidate particles
-// (the cell-list rows near the brick, with each row's x-range cut to the
-// support circle) through wave-uniform scalar loads; the x-y distance is
-// computed once per candidate and shared by the lane's four voxels, and a
-// candidate or voxel that no lane reaches is skipped wave-wide.  Every voxel
-// adds its terms in cell-row order, then particle index order, so the field
-// is bitwise repeatable.  Workgroups are remapped so that each XCD
-// (workgroups are dealt round-robin over the 8 XCDs) walks a contiguous run
-// of bricks and keeps its particle rows in its own L2.
-__global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
-                                               const float4 *__restrict__ parts, int32_t nbricks, int32_t per_xcd,
-                                               float *__restrict__ dn)
+// One workgroup per brick of 8 x 8 x 4 voxels; in each of its four waves, lane
+// (lane & 7, lane >> 3) owns the column of four voxels along z.  The brick's
+// cell-list rows near it (each row's x-range cut to the support circle) are
+// dealt round-robin to its four waves, whose lanes walk the row's candidate
+// particles through wave-uniform scalar loads; the x-y distance is computed
+// once per candidate and shared by the lane's four voxels, and a candidate or
+// voxel that no lane reaches is skipped wave-wide.  The four partial sums are
+// added in wave order through LDS, and each wave adds its terms in row order,
+// then particle index order, so the field is bitwise repeatable.  Splitting a
+// brick four ways gives four times as many work units as wave slots, so the
+// dispatcher balances bricks of unequal cost.  Workgroups are remapped so
+// that each XCD (workgroups are dealt round-robin over the 8 XCDs) walks a
+// contiguous run of bricks and keeps its particle rows in its own L2.
+// waves per brick (4: 0.565 ms at config 2; 8: 0.621 ms; 1: 0.649 ms)
+constexpr int SPLAT_WAVES = 4;
+
+__global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
+                                                            const float4 *__restrict__ parts, int32_t nbricks,
+                                                            int32_t per_xcd, float *__restrict__ dn)
 {
-    const int32_t logical = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    __shared__ float partial[SPLAT_WAVES - 1][SPLAT_BZ][64];
+    const int32_t brick = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    if (brick >= nbricks) return;   // uniform over the workgroup
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int32_t brick = logical * 4 + wave;
-    if (brick >= nbricks) return;
     const int lane = threadIdx.x & 63;
     const int32_t bx = brick % P.nbx;
     const int32_t by = (brick / P.nbx) % P.nby;
@@ -352,44 +358,61 @@ __global__ __launch_bounds__(256) void k_splat(SplatParams P, const uint32_t *__
     const int cz1 = min(cg.nc[2] - 1, (int)floorf((bhi[2] + R - cg.clo[2]) * cg.inv_cell) + 1);
     const int cy0 = max(0, (int)floorf((blo[1] - R - cg.clo[1]) * cg.inv_cell) - 1);
     const int cy1 = min(cg.nc[1] - 1, (int)floorf((bhi[1] + R - cg.clo[1]) * cg.inv_cell) + 1);
+    const int ny = cy1 - cy0 + 1;
 
     float acc[SPLAT_BZ];
 #pragma unroll
     for (int v = 0; v < SPLAT_BZ; ++v) acc[v] = 0.0f;
-    for (int kz = cz0; kz <= cz1; ++kz) {
+    // rows (kz, ky) in order, every SPLAT_WAVES-th from the wave's index (no rows
+    // if the y range is empty, so the row stepping below always advances)
+    int kz = ny >= 1 ? cz0 : cz1 + 1, ky = cy0 + wave;
+    for (;;) {
+        while (ky > cy1) {
+            ky -= ny;
+            ++kz;
+        }
+        if (kz > cz1) break;
+        const int kyr = ky;
+        ky += SPLAT_WAVES;
         const float zl = cg.clo[2] + (float)kz * cg.cell;
         const float gz = fmaxf(0.0f, fmaxf(zl - bhi[2], blo[2] - (zl + cg.cell)));
-        for (int ky = cy0; ky <= cy1; ++ky) {
-            const float yl = cg.clo[1] + (float)ky * cg.cell;
-            const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
-            // 1.0001 R^2 keeps the cull conservative under rounding (and the
-            // 1-ulp hardware square root)
-            const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
-            if (rem <= 0.0f) continue;
-            const float dxm = __builtin_amdgcn_sqrtf(rem);
-            const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
-            const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
-            if (kx0 > kx1) continue;
-            const int row = (kz * cg.nc[1] + ky) * cg.nc[0];
-            const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
-            const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
-            // two records per iteration: one wider scalar load and one wait
-            // for both, half the loop overhead; the terms are still added in
-            // index order
-            uint32_t s = s0;
-            for (; s + 1 < s1; s += 2) {
-                const float4 qa = parts[s], qb = parts[s + 1];
-                splat_candidate(P, cx, cy, cz, qa, acc);
-                splat_candidate(P, cx, cy, cz, qb, acc);
-            }
-            if (s < s1) splat_candidate(P, cx, cy, cz, parts[s], acc);
+        const float yl = cg.clo[1] + (float)kyr * cg.cell;
+        const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
+        // 1.0001 R^2 keeps the cull conservative under rounding (and the
+        // 1-ulp hardware square root)
+        const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
+        if (rem <= 0.0f) continue;
+        const float dxm = __builtin_amdgcn_sqrtf(rem);
+        const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
+        const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
+        if (kx0 > kx1) continue;
+        const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
+        const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
+        const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
+        // two records per iteration: one wider scalar load and one wait for
+        // both, half the loop overhead; the terms are still added in index order
+        uint32_t s = s0;
+        for (; s + 1 < s1; s += 2) {
+            const float4 qa = parts[s], qb = parts[s + 1];
+            splat_candidate(P, cx, cy, cz, qa, acc);
+            splat_candidate(P, cx, cy, cz, qb, acc);
         }
+        if (s < s1) splat_candidate(P, cx, cy, cz, parts[s], acc);
     }
-    if (vx < P.res[0] && vy < P.res[1]) {
+    if (wave > 0) {
 #pragma unroll
-        for (int v = 0; v < SPLAT_BZ; ++v)
-            if (vz0 + v < P.res[2])
-                dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = acc[v] * (0.25f * P.scale);
+        for (int v = 0; v < SPLAT_BZ; ++v) partial[wave - 1][v][lane] = acc[v];
+    }
+    __syncthreads();
+    if (wave == 0 && vx < P.res[0] && vy < P.res[1]) {
+        const float sc = 0.25f * P.scale;
+#pragma unroll
+        for (int v = 0; v < SPLAT_BZ; ++v) {
+            float sum = acc[v];
+#pragma unroll
+            for (int w = 0; w < SPLAT_WAVES - 1; ++w) sum += partial[w][v][lane];
+            if (vz0 + v < P.res[2]) dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = sum * sc;
+        }
     }
 }
 
@@ -710,9 +733,8 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
                         const KTimer &t)
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
-    const int32_t nblocks = (nbricks + 3) / 4;
-    const int32_t per_xcd = (nblocks + 7) / 8;
-    hipExtLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, t.start, t.stop, 0, P, start,
+    const int32_t per_xcd = (nbricks + 7) / 8;
+    hipExtLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(64 * SPLAT_WAVES), 0, s, t.start, t.stop, 0, P, start,
                           sorted, nbricks, per_xcd, dn);
     return hipGetLastError();
 }
