@@ -65,22 +65,23 @@ def measured_traffic(kernel: str, row: str, config: int, dtype: str):
             "write_scale": c["calibration"]["write_scale"], "source": "profiles/counters_config2_f32.md"}
 
 
-def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat",)):
+def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat",), live_every: int = 4):
     """ms per step over exactly `steps` steps (host clock between two device
     synchronisations) with the `live` kernel groups timed by their own
-    dispatch events inside those steps; then a second pass of the same length
-    for per-step latencies and the other groups' times.  Every timed group and
-    every event record costs the stream microseconds, so the timed pass
-    carries only what the roofline needs."""
+    dispatch events inside those steps (every `live_every`-th step, the first
+    included); then a second pass of the same length for per-step latencies
+    and the other groups' times.  Every timed launch and every event record
+    costs the stream microseconds, so the timed pass carries only what the
+    roofline needs."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ctx.profile_read("march", reset=True)
     ctx.profile_select(live)
-    ctx.profile_enable(True)
     t0 = time.perf_counter()
     for i in range(steps):
+        ctx.profile_enable(i % live_every == 0)
         fn()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -377,7 +378,7 @@ def main(argv=None):
                       "unit": "TFLOP/s", "frac": tf / FP32_PEAK_TFLOPS, "traffic": None,
                       "per_unit": "25 FP32 flops per (voxel, particle) pair within 2h",
                       "launch_ms": avg["splat"], "units_per_launch": pairs,
-                      "launch_timing": "dispatch events of the kernel inside the timed steps"}
+                      "launch_timing": "dispatch events of the kernel in every 4th of the timed steps"}
         tr = measured_traffic("k_splat", "k_splat", args.config, args.dtype)
         if tr is not None and args.splat == "gather":
             splat_roof["traffic"] = tr["bytes"]
