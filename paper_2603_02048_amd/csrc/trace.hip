@@ -125,13 +125,15 @@ __device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3
 // Exit distance along w from a point in the volume (clamped at 0).
 __device__ __forceinline__ float exit_distance(const TraceGrid &G, const float c[3], const float w[3])
 {
+    // per axis the face the ray heads for, chosen by value (a per-lane choice
+    // of address would turn the uniform bounds into vector loads), and the
+    // distance by the hardware reciprocal (~2 ulp); axes with w = 0 never exit
     float t = INFINITY;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (w[k] > 0.0f)
-            t = fminf(t, (G.hi[k] - c[k]) / w[k]);
-        else if (w[k] < 0.0f)
-            t = fminf(t, (G.lo[k] - c[k]) / w[k]);
+        const float face = w[k] > 0.0f ? G.hi[k] : G.lo[k];
+        const float tk = (face - c[k]) * __builtin_amdgcn_rcpf(w[k]);
+        if (w[k] != 0.0f) t = fminf(t, tk);
     }
     return fmaxf(t, 0.0f);
 }
