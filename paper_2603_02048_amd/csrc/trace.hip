@@ -501,7 +501,7 @@ __device__ __forceinline__ float face_distance(const TraceGrid &G, const float c
 // every step is tested against those (L.ninner of them) and the first one
 // crossed ends the ray at the crossing point.
 template <int DT, int SCENE>
-__global__ __launch_bounds__(256) void k_march(TraceLaunch L)
+__device__ __forceinline__ void march(const TraceLaunch &L)
 {
     const TraceGrid &G = L.grid;
     const TraceStep &S = L.step;
@@ -536,11 +536,20 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
     float safe = 0.0f;   // lower bound of the distance from c to the box faces
     uint32_t steps = 0;
     float side[SCENE == 2 ? kMaxInner : 1];   // side values of the inner boards at c
+    // A finished ray keeps its end state (c, w, steps) and writes its outputs
+    // only when the wave refills or stops, so the output code runs once for
+    // all lanes finished since, not once per finishing lane.
+    int fin = -1;        // status of a finished ray not yet written (-1: none)
+    int fin_surf = -1;   // its board (c is then the hit point), -1 for none
 
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (!done && (nidle >= refill_min || idle == ~0ull)) {
+            if (fin >= 0) {
+                finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
+                fin = -1;
+            }
             if (next == end) {
                 uint32_t b;
                 if (pending) {
@@ -599,7 +608,10 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
             }
             continue;
         }
-        if (done && idle == ~0ull) break;
+        if (done && idle == ~0ull) {
+            if (fin >= 0) finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
+            break;
+        }
         if (!active) continue;
 
         // ---- one step of Eq. 16 with the step of Eq. 18 ----
@@ -679,7 +691,9 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
             if (!(pn2 > 0.0f && pn2 < INFINITY && fabsf(n) < INFINITY))
                 status = 3;
             else if (SCENE == 2 && surf >= 0) {
-                finish_ray<true>(L, r, hp, w, steps, 0, hp, surf);
+                c[0] = hp[0]; c[1] = hp[1]; c[2] = hp[2];
+                fin = 0;
+                fin_surf = surf;
                 active = false;
                 continue;
             } else if (safe <= S.pos_eps &&
@@ -690,10 +704,35 @@ __global__ __launch_bounds__(256) void k_march(TraceLaunch L)
                 status = 1;
         }
         if (status >= 0) {
-            finish_ray<SCENE != 0>(L, r, c, w, steps, status);
+            fin = status;
+            fin_surf = -1;
             active = false;
         }
     }
+}
+
+// Without boards, or with boards only outside the volume, the march fits six
+// waves per SIMD (at most 80 VGPRs) with no spills; the board-crossing
+// variant fits five (capped at six, it would spill).
+template <int DT, int SCENE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_march(TraceLaunch L)
+{
+    march<DT, SCENE>(L);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_march_boards(TraceLaunch L)
+{
+    march<DT, 2>(L);
+}
+
+template <int DT, int SCENE>
+static constexpr auto march_kernel()
+{
+    if constexpr (SCENE == 2)
+        return &k_march_boards<DT>;
+    else
+        return &k_march<DT, SCENE>;
 }
 
 // ---------------------------------------------------------------------------
@@ -718,11 +757,14 @@ template <int SCENE>
 static void launch_march_t(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s, const KTimer &t)
 {
     if (dtype == DT_F32)
-        hipExtLaunchKernelGGL((k_march<DT_F32, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
+        hipExtLaunchKernelGGL((march_kernel<DT_F32, SCENE>()), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0,
+                              L);
     else if (dtype == DT_F16)
-        hipExtLaunchKernelGGL((k_march<DT_F16, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
+        hipExtLaunchKernelGGL((march_kernel<DT_F16, SCENE>()), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0,
+                              L);
     else
-        hipExtLaunchKernelGGL((k_march<DT_BF16, SCENE>), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop, 0, L);
+        hipExtLaunchKernelGGL((march_kernel<DT_BF16, SCENE>()), dim3(march_blocks), dim3(256), 0, s, t.start, t.stop,
+                              0, L);
 }
 
 hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s, const KTimer &t)
@@ -741,9 +783,11 @@ int march_scene_mode(const TraceLaunch &L) { return L.ninner > 0 ? 2 : L.nquads 
 template <int SCENE>
 static hipError_t occupancy(int dtype, int *nb)
 {
-    if (dtype == DT_F32) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_F32, SCENE>, 256, 0);
-    if (dtype == DT_F16) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_F16, SCENE>, 256, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_march<DT_BF16, SCENE>, 256, 0);
+    if (dtype == DT_F32)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, march_kernel<DT_F32, SCENE>(), 256, 0);
+    if (dtype == DT_F16)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, march_kernel<DT_F16, SCENE>(), 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, march_kernel<DT_BF16, SCENE>(), 256, 0);
 }
 
 int march_blocks_per_cu(int dtype, int scene_mode)
