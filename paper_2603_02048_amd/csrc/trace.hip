@@ -431,9 +431,9 @@ __device__ __forceinline__ float4 half4_to_float4(uint32_t lo, uint32_t hi)
 }
 
 template <int DT>
-__device__ __forceinline__ void load_xpair(const void *__restrict__ f, uint32_t i, float4 &a, float4 &b)
+__device__ __forceinline__ void load_xpair_at(gpair_ptr p, float4 &a, float4 &b)
 {
-    const u32x4_a8 v = *(gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * (size_t)i);
+    const u32x4_a8 v = *p;
     a = half4_to_float4<DT>(v.x, v.y);
     b = half4_to_float4<DT>(v.z, v.w);
 }
@@ -446,21 +446,29 @@ __device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *_
     cell_of<DT>(G, x, b, t);
     const uint32_t sy = (uint32_t)G.res[0], sz = (uint32_t)G.res[0] * (uint32_t)G.res[1];
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
+    // Addresses by 64-bit pointer steps from the corner voxel: the x-neighbour
+    // is the load's immediate offset, and the y and z rows one add each
+    // (instead of a 32-bit index and a 64-bit address per load).
     if (DT == DT_F32) {
-        gfloat4_ptr F = (gfloat4_ptr)f;
-        c000 = load_f32x4(F, b);
-        c100 = load_f32x4(F, b + 1);
-        c010 = load_f32x4(F, b + sy);
-        c110 = load_f32x4(F, b + sy + 1);
-        c001 = load_f32x4(F, b + sz);
-        c101 = load_f32x4(F, b + sz + 1);
-        c011 = load_f32x4(F, b + sz + sy);
-        c111 = load_f32x4(F, b + sz + sy + 1);
+        const gfloat4_ptr p0 = (gfloat4_ptr)f + b, p1 = p0 + sz;
+        const gfloat4_ptr q0 = p0 + sy, q1 = p1 + sy;
+        c000 = load_f32x4(p0, 0);
+        c100 = load_f32x4(p0, 1);
+        c010 = load_f32x4(q0, 0);
+        c110 = load_f32x4(q0, 1);
+        c001 = load_f32x4(p1, 0);
+        c101 = load_f32x4(p1, 1);
+        c011 = load_f32x4(q1, 0);
+        c111 = load_f32x4(q1, 1);
     } else {
-        load_xpair<DT>(f, b, c000, c100);
-        load_xpair<DT>(f, b + sy, c010, c110);
-        load_xpair<DT>(f, b + sz, c001, c101);
-        load_xpair<DT>(f, b + sz + sy, c011, c111);
+        const gpair_ptr p0 = (gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * (size_t)b);
+        const gpair_ptr p1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sz);
+        const gpair_ptr q0 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sy);
+        const gpair_ptr q1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p1 + 4 * (size_t)sy);
+        load_xpair_at<DT>(p0, c000, c100);
+        load_xpair_at<DT>(q0, c010, c110);
+        load_xpair_at<DT>(p1, c001, c101);
+        load_xpair_at<DT>(q1, c011, c111);
     }
     // trilinear weights, then one FMA per corner and channel
     const float ux = 1.0f - t[0], uy = 1.0f - t[1], uz = 1.0f - t[2];
