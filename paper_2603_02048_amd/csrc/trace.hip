@@ -645,9 +645,12 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 ds = S.ds_uniform;
             } else {
                 const float pgn = __builtin_amdgcn_sqrtf(pg0 * pg0 + pg1 * pg1 + pg2 * pg2);
-                ds = fminf(fmaxf(n * S.theta_max * __builtin_amdgcn_rcpf(pgn + S.eps), S.ds_min), S.ds_max);
+                // clamp to [ds_min, ds_max] (ds_min <= ds_max, checked on the host) in
+                // one med3: fminf/fmaxf would also canonicalize both bounds every step
+                ds = __builtin_amdgcn_fmed3f(n * S.theta_max * __builtin_amdgcn_rcpf(pgn + S.eps), S.ds_min,
+                                             S.ds_max);
             }
-            ds = fminf(ds, te);
+            ds = te < ds ? te : ds;   // min(ds, te) as a select: fminf would canonicalize both
             // omega_{k+1} = normalize(omega_k + ds/n P g) = normalize(p + |p| ds/n P g)
             const float a = ds * rn * pnorm;
             dw[0] = fmaf(a, pg0, dw[0]);
