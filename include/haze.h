@@ -97,18 +97,20 @@ const char *hz_last_error(void);
 hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 
 /* Tuning knobs.  The march knobs change speed only, never results; the splat
- * method changes only how delta_n is rounded (both meet the same accuracy and
- * each is bitwise repeatable):
+ * method and brick depth change only how delta_n is rounded (all meet the same
+ * accuracy and each is bitwise repeatable):
  *   "march.refill_min"     refill a wave once this many of its 64 lanes are
  *                          idle, 1..64 (default 16)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
- *   "splat.method"         0 or 1: gather (one wave per 8x8x4 voxel brick,
- *                          fixed FP32 summation order; the default), 2: scatter
+ *   "splat.method"         0 or 1: gather (one workgroup per 8x8xBZ voxel
+ *                          brick, fixed FP32 summation order; the default), 2: scatter
  *                          (voxel tiles with 64-bit fixed-point accumulation in
  *                          LDS; slower, for a support of up to ~16 cells per
  *                          tile axis, HZ_E_UNSUPPORTED beyond); both are
  *                          bitwise repeatable
+ *   "splat.brick_z"        gather brick depth BZ: 4 or 8 voxels, 0 = the one
+ *                          that makes the brick closer to a cube (default 0)
  * Errors: HZ_E_INVALID (unknown key or value out of range). */
 hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 

@@ -36,15 +36,17 @@ struct CellGrid {
     int32_t ncells;
 };
 
-// Gather-splat brick: 8 x 8 lanes in x-y, each lane a column of 4 voxels in z.
-constexpr int SPLAT_BX = 8, SPLAT_BY = 8, SPLAT_BZ = 4;
+// Gather-splat brick: 8 x 8 lanes in x-y, each lane a column of bz voxels in z
+// (4 or 8, whichever makes the brick closer to a cube).
+constexpr int SPLAT_BX = 8, SPLAT_BY = 8;
 
 // Geometry and constants of one splat launch.
 struct SplatParams {
     float lo[3];          // grid box corner
     float sp[3];          // voxel spacing
     int32_t res[3];
-    int32_t nbx, nby, nbz; // gather bricks (SPLAT_BX x SPLAT_BY x SPLAT_BZ voxels) per axis
+    int32_t bz;            // gather brick depth: 4 or 8 voxels
+    int32_t nbx, nby, nbz; // gather bricks (SPLAT_BX x SPLAT_BY x bz voxels) per axis
     float h;
     float inv_h;
     float support2;       // (2h)^2

@@ -131,6 +131,7 @@ struct hz_ctx {
     int32_t refill_min = 16;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
+    int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8
     std::vector<hz_field *> fields;
     std::mutex fields_mu;
     // memory of released fields, reused in stream order (no host sync)
@@ -525,6 +526,10 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
     } else if (k == "march.blocks_per_cu") {
         if (value < 0 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.blocks_per_cu must be in [0, 64]");
         c->blocks_per_cu = (int32_t)value;
+    } else if (k == "splat.brick_z") {
+        if (value != 0 && value != 4 && value != 8)
+            return fail(HZ_E_INVALID, "hz_ctx_tune: splat.brick_z must be 0, 4 or 8");
+        c->splat_brick_z = (int32_t)value;
     } else if (k == "splat.method") {
         if (value < 0 || value > 2) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.method must be 0, 1 or 2");
         c->splat_method = (int32_t)value;
@@ -723,7 +728,13 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     }
     sp.nbx = (g->res[0] + SPLAT_BX - 1) / SPLAT_BX;
     sp.nby = (g->res[1] + SPLAT_BY - 1) / SPLAT_BY;
-    sp.nbz = (g->res[2] + SPLAT_BZ - 1) / SPLAT_BZ;
+    // brick depth: the one of 4 or 8 voxels that makes the brick closer to a
+    // cube (8 when the z spacing is below sqrt(2) times the x-y spacing)
+    if (c->splat_brick_z == 4 || c->splat_brick_z == 8)
+        sp.bz = c->splat_brick_z;
+    else
+        sp.bz = (double)sp.sp[2] < 1.41421356 * 0.5 * ((double)sp.sp[0] + (double)sp.sp[1]) ? 8 : 4;
+    sp.nbz = (g->res[2] + sp.bz - 1) / sp.bz;
     sp.h = prm->h;
     sp.inv_h = (float)(1.0 / h);
     sp.support2 = (float)(4.0 * h * h);

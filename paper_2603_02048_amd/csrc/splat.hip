@@ -280,7 +280,8 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
     sorted[b + rank] = rec;
 }
 
-// Adds one candidate particle's M4-spline terms to the lane's column of voxels.
+// Adds one candidate particle's M4-spline terms to the lane's column of BZ voxels.
+template <int BZ>
 __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, float cy, const float *cz,
                                                 const float4 &q, float *acc)
 {
@@ -288,7 +289,7 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
     const float dxy = fmaf(dx, dx, dy * dy);
     if (dxy < P.support2) {
 #pragma unroll
-        for (int v = 0; v < SPLAT_BZ; ++v) {
+        for (int v = 0; v < BZ; ++v) {
             const float dz = cz[v] - q.z;
             const float r2 = fmaf(dz, dz, dxy);
             if (r2 < P.support2) {
@@ -305,12 +306,12 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
     }
 }
 
-// One workgroup per brick of 8 x 8 x 4 voxels; in each of its four waves, lane
-// (lane & 7, lane >> 3) owns the column of four voxels along z.  The brick's
+// One workgroup per brick of 8 x 8 x BZ voxels (BZ = 4 or 8); in each of its
+// four waves, lane (lane & 7, lane >> 3) owns the column of BZ voxels along z.  The brick's
 // cell-list rows near it (each row's x-range cut to the support circle) are
 // dealt round-robin to its four waves, whose lanes walk the row's candidate
 // particles through wave-uniform scalar loads; the x-y distance is computed
-// once per candidate and shared by the lane's four voxels, and a candidate or
+// once per candidate and shared by the lane's column, and a candidate or
 // voxel that no lane reaches is skipped wave-wide.  The four partial sums are
 // added in wave order through LDS, and each wave adds its terms in row order,
 // then particle index order, so the field is bitwise repeatable.  Splitting a
@@ -321,11 +322,12 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
 // waves per brick (4: 0.565 ms at config 2; 8: 0.621 ms; 1: 0.649 ms)
 constexpr int SPLAT_WAVES = 4;
 
+template <int BZ>
 __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
                                                             const float4 *__restrict__ parts, int32_t nbricks,
                                                             int32_t per_xcd, float *__restrict__ dn)
 {
-    __shared__ float partial[SPLAT_WAVES - 1][SPLAT_BZ][64];
+    __shared__ float partial[SPLAT_WAVES - 1][BZ][64];
     const int32_t brick = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
     if (brick >= nbricks) return;   // uniform over the workgroup
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -333,18 +335,18 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     const int32_t bx = brick % P.nbx;
     const int32_t by = (brick / P.nbx) % P.nby;
     const int32_t bz = brick / (P.nbx * P.nby);
-    const int32_t vx = bx * SPLAT_BX + (lane & 7), vy = by * SPLAT_BY + (lane >> 3), vz0 = bz * SPLAT_BZ;
+    const int32_t vx = bx * SPLAT_BX + (lane & 7), vy = by * SPLAT_BY + (lane >> 3), vz0 = bz * BZ;
     const float cx = P.lo[0] + ((float)vx + 0.5f) * P.sp[0];
     const float cy = P.lo[1] + ((float)vy + 0.5f) * P.sp[1];
-    float cz[SPLAT_BZ];
+    float cz[BZ];
 #pragma unroll
-    for (int v = 0; v < SPLAT_BZ; ++v) cz[v] = P.lo[2] + ((float)(vz0 + v) + 0.5f) * P.sp[2];
+    for (int v = 0; v < BZ; ++v) cz[v] = P.lo[2] + ((float)(vz0 + v) + 0.5f) * P.sp[2];
 
     // brick AABB of voxel centres (wave-uniform)
     float blo[3], bhi[3];
     {
         const int32_t b0[3] = {bx * SPLAT_BX, by * SPLAT_BY, vz0};
-        const int32_t bd[3] = {SPLAT_BX, SPLAT_BY, SPLAT_BZ};
+        const int32_t bd[3] = {SPLAT_BX, SPLAT_BY, BZ};
         for (int a = 0; a < 3; ++a) {
             const int32_t i1 = min(b0[a] + bd[a] - 1, P.res[a] - 1);
             blo[a] = P.lo[a] + ((float)b0[a] + 0.5f) * P.sp[a];
@@ -360,9 +362,9 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     const int cy1 = min(cg.nc[1] - 1, (int)floorf((bhi[1] + R - cg.clo[1]) * cg.inv_cell) + 1);
     const int ny = cy1 - cy0 + 1;
 
-    float acc[SPLAT_BZ];
+    float acc[BZ];
 #pragma unroll
-    for (int v = 0; v < SPLAT_BZ; ++v) acc[v] = 0.0f;
+    for (int v = 0; v < BZ; ++v) acc[v] = 0.0f;
     // rows (kz, ky) in order, every SPLAT_WAVES-th from the wave's index (no rows
     // if the y range is empty, so the row stepping below always advances)
     int kz = ny >= 1 ? cz0 : cz1 + 1, ky = cy0 + wave;
@@ -394,20 +396,20 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
         uint32_t s = s0;
         for (; s + 1 < s1; s += 2) {
             const float4 qa = parts[s], qb = parts[s + 1];
-            splat_candidate(P, cx, cy, cz, qa, acc);
-            splat_candidate(P, cx, cy, cz, qb, acc);
+            splat_candidate<BZ>(P, cx, cy, cz, qa, acc);
+            splat_candidate<BZ>(P, cx, cy, cz, qb, acc);
         }
-        if (s < s1) splat_candidate(P, cx, cy, cz, parts[s], acc);
+        if (s < s1) splat_candidate<BZ>(P, cx, cy, cz, parts[s], acc);
     }
     if (wave > 0) {
 #pragma unroll
-        for (int v = 0; v < SPLAT_BZ; ++v) partial[wave - 1][v][lane] = acc[v];
+        for (int v = 0; v < BZ; ++v) partial[wave - 1][v][lane] = acc[v];
     }
     __syncthreads();
     if (wave == 0 && vx < P.res[0] && vy < P.res[1]) {
         const float sc = 0.25f * P.scale;
 #pragma unroll
-        for (int v = 0; v < SPLAT_BZ; ++v) {
+        for (int v = 0; v < BZ; ++v) {
             float sum = acc[v];
 #pragma unroll
             for (int w = 0; w < SPLAT_WAVES - 1; ++w) sum += partial[w][v][lane];
@@ -734,8 +736,11 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
     const int32_t per_xcd = (nbricks + 7) / 8;
-    hipExtLaunchKernelGGL(k_splat, dim3((unsigned)(per_xcd * 8)), dim3(64 * SPLAT_WAVES), 0, s, t.start, t.stop, 0, P, start,
-                          sorted, nbricks, per_xcd, dn);
+    const dim3 g((unsigned)(per_xcd * 8)), b(64 * SPLAT_WAVES);
+    if (P.bz == 8)
+        hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn);
+    else
+        hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn);
     return hipGetLastError();
 }
 

@@ -46,14 +46,27 @@ def _splat_both(ctx, haze, wl, dtype="f32", scale=1.0):
     return field, md
 
 
-SPLAT_METHODS = {"gather": 1, "scatter": 2}
+# splat kernels: (splat.method, splat.brick_z); the gather brick depth is
+# chosen per grid by default and forced here so both depths are checked
+SPLAT_METHODS = {"gather": (1, 4), "gather8": (1, 8), "scatter": (2, 0)}
 
 
-@pytest.mark.parametrize("method", ["gather", "scatter"])
+def _use(ctx, method):
+    m, bz = SPLAT_METHODS[method]
+    ctx.tune("splat.method", m)
+    ctx.tune("splat.brick_z", bz)
+
+
+def _default(ctx):
+    ctx.tune("splat.method", 0)
+    ctx.tune("splat.brick_z", 0)
+
+
+@pytest.mark.parametrize("method", ["gather", "gather8", "scatter"])
 @pytest.mark.parametrize("seed,res,h", [(0, (21, 17, 13), 0.03), (1, (8, 9, 30), 0.05), (2, (2, 3, 2), 0.2),
                                         (3, (40, 33, 19), 0.02)])
 def test_splat_parity_small(ctx, haze, seed, res, h, method):
-    ctx.tune("splat.method", SPLAT_METHODS[method])
+    _use(ctx, method)
     try:
         wl = W.make_small(seed=seed, res=res, h=h, n=6000)
         field, md = _splat_both(ctx, haze, wl)
@@ -63,12 +76,12 @@ def test_splat_parity_small(ctx, haze, seed, res, h, method):
                            f"splat {method} seed={seed} res={res}")
         field.release()
     finally:
-        ctx.tune("splat.method", 0)
+        _default(ctx)
 
 
-@pytest.mark.parametrize("method", ["gather", "scatter"])
+@pytest.mark.parametrize("method", ["gather", "gather8", "scatter"])
 def test_splat_is_bitwise_repeatable(ctx, haze, method):
-    ctx.tune("splat.method", SPLAT_METHODS[method])
+    _use(ctx, method)
     try:
         wl = W.make_small(seed=3, n=5000)
         parts = haze.upload_particles(wl.particles)
@@ -80,7 +93,7 @@ def test_splat_is_bitwise_repeatable(ctx, haze, method):
         f1.release()
         f2.release()
     finally:
-        ctx.tune("splat.method", 0)
+        _default(ctx)
 
 
 def test_splat_methods_on_config2(ctx, haze):
@@ -89,13 +102,13 @@ def test_splat_methods_on_config2(ctx, haze):
     md = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h)
     ref = md.arrays
     parts = haze.upload_particles(wl.particles)
-    for method, code in SPLAT_METHODS.items():
-        ctx.tune("splat.method", code)
+    for method in SPLAT_METHODS:
+        _use(ctx, method)
         f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
         dn, gx, gy, gz = _field_np(ctx, f)
         assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing, f"config2 splat {method}")
         f.release()
-    ctx.tune("splat.method", 0)
+    _default(ctx)
 
 
 def test_splat_particles_outside_grid(ctx, haze):
@@ -124,7 +137,7 @@ def test_splat_cell_scan_paths(ctx, haze):
     refs = {}
     for wl, method in ((small, "gather"), (fine, "gather"), (small, "gather"), (small, "scatter"),
                        (small, "gather"), (fine, "gather"), (fine, "gather")):
-        ctx.tune("splat.method", SPLAT_METHODS[method])
+        _use(ctx, method)
         try:
             if wl.name + str(wl.h) not in refs:
                 refs[wl.name + str(wl.h)] = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h).arrays
@@ -137,7 +150,7 @@ def test_splat_cell_scan_paths(ctx, haze):
             assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], wl.grid.spacing, f"scan paths h={wl.h} {method}")
             f.release()
         finally:
-            ctx.tune("splat.method", 0)
+            _default(ctx)
 
 
 @pytest.mark.parametrize("kgd", [1.0, 200.0])
