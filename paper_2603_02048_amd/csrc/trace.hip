@@ -570,13 +570,13 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 }
                 b = __builtin_amdgcn_readfirstlane(b);
                 if (b >= nh) {
-                    done = true;
-                    continue;
+                    done = true;   // next == end: nothing left to hand out below
+                } else {
+                    next = b;
+                    end = min(b + 64u, nh);
                 }
-                next = b;
-                end = min(b + 64u, nh);
             }
-            if (!active) {
+            if (!active && next < end) {
                 const uint32_t k = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 if (k < end) {
@@ -606,7 +606,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 }
             }
             next = min(next + nidle, end);
-            if (next == end && !pending) {
+            if (!done && next == end && !pending) {
                 if (dyn0 >= nh) {
                     done = true;   // the static batches hold every hit: no dynamic work
                 } else {
@@ -614,9 +614,10 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                     pending = true;
                 }
             }
-            continue;
         }
-        if (done && idle == ~0ull) {
+        // The refilled lanes step in the same iteration; the loop has one
+        // back-edge, so loop-carried values need no register copies.
+        if (done && __ballot(active) == 0ull) {
             if (fin >= 0) finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
             break;
         }
@@ -624,6 +625,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
 
         // ---- one step of Eq. 16 with the step of Eq. 18 ----
         int status = -1;
+        int hit_surf = -1;
         float te = INFINITY;
         bool near = safe <= S.near_cap;
         if (near) {
@@ -703,10 +705,8 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 status = 3;
             else if (SCENE == 2 && surf >= 0) {
                 c[0] = hp[0]; c[1] = hp[1]; c[2] = hp[2];
-                fin = 0;
-                fin_surf = surf;
-                active = false;
-                continue;
+                status = 0;
+                hit_surf = surf;
             } else if (safe <= S.pos_eps &&
                      (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] || c[2] < G.lo[2] ||
                       c[2] > G.hi[2]))
@@ -716,7 +716,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
         }
         if (status >= 0) {
             fin = status;
-            fin_surf = -1;
+            fin_surf = hit_surf;
             active = false;
         }
     }
