@@ -8,17 +8,18 @@
 // Pipeline (all integer work exact, so the result is bitwise repeatable):
 //   k_cell_count   particle -> cell id (cells of edge h over the grid box grown
 //                  by 2h), integer histogram with atomics
-//   k_scan_*       exclusive prefix sum of the histogram (tile sums, scan of
-//                  the tile sums, tiles rescanned with their offsets)
+//   k_scan_onepass exclusive prefix sum of the histogram in one launch
+//                  (tile sums published with tickets, lower tiles added);
+//                  k_scan_* in three passes for very large cell counts
 //   k_cell_scatter particle index -> its slot (cell start + arrival rank from
 //                  the histogram atomics: an arbitrary order inside the cell)
 //   k_cell_order   per particle, its rank by index among its cell's members
 //                  (stable order); (x, y, z, m) into cell-sorted float4 records
-//   k_splat        one wave per 8x8x4 voxel brick: every lane owns a column of
-//                  4 voxels and all lanes walk the same candidate particles
-//                  (wave-uniform scalar loads) row by row of the cell list,
-//                  culled by the brick-to-row distance, summing m_j W in a
-//                  fixed order
+//   k_splat        one workgroup per 8x8x4 or 8x8x8 voxel brick, its cell-list
+//                  rows dealt to four waves: every lane owns a column of
+//                  voxels and the wave's lanes walk the same candidate
+//                  particles (wave-uniform scalar loads), culled by the
+//                  brick-to-row distance, summing m_j W in a fixed order
 //   k_splat_scatter  alternative: voxel tiles with 64-bit fixed-point LDS
 //                  accumulators, particles walking their footprints (more
 //                  accurate, bitwise repeatable, but about 2x slower than the

@@ -11,18 +11,20 @@
 // caption); the image is formed only by bending (Sec. 3.3.2): the exit ray is
 // intersected with a backdrop plane and re-projected through the same pinhole.
 //
-// Two launches per trace:
+// Three launches per trace:
 //   k_raygen  one thread per queue slot: pinhole ray, slab test against the
 //             volume; rays that miss are finished at once, rays that enter
-//             are binned by their chord length (longest first) and counted
+//             are binned by their chord length (longest first) and counted;
+//             it also clears the counter set of the next launch
 //   k_raygen_place  places the entering rays in a hit list sorted by bin
 //             (wave ballots + mbcnt ranks, one atomic per workgroup and bin)
 //   k_march   persistent waves pull hit rays from the list; when enough lanes
 //             have finished, the idle lanes are refilled together (ballot of
 //             idle lanes, one atomic per wave, mbcnt rank), which keeps the
 //             wave busy despite the spread of step counts adaptive stepping
-//             causes.  Each ray's arithmetic is independent of which lane or
-//             wave runs it, so results are bitwise repeatable.
+//             causes; finished rays write their outputs at the next refill.
+//             Each ray's arithmetic is independent of which lane or wave runs
+//             it, so results are bitwise repeatable.
 //
 // Positions are float32 metres with a compensated (Kahan) sum of the steps.
 // The direction is carried as an unnormalised vector p = wr + dw (entry
