@@ -278,13 +278,19 @@ __global__ void k_trace_init(uint32_t *counters)
 __device__ __forceinline__ uint32_t bin_rank(int bin, uint32_t (*wcnt)[kRayBins])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < kRayBins) wcnt[wave][lane] = 0u;
+    // only the bins present in the wave (a wave is a pixel tile, whose rays
+    // have similar chords: usually one to three bins)
     uint32_t rank = 0;
-#pragma unroll
-    for (int b = 0; b < kRayBins; ++b) {
+    uint64_t todo = __ballot(bin < kRayBins);
+    while (todo) {
+        const int first = (int)__builtin_ctzll(todo);
+        const int b = __builtin_amdgcn_readfirstlane(__shfl(bin, first));
         const uint64_t m = __ballot(bin == b);
         if (lane == 0) wcnt[wave][b] = (uint32_t)__popcll(m);
         if (bin == b)
             rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        todo &= ~m;
     }
     return rank;
 }
