@@ -124,3 +124,55 @@ def test_field_written_on_one_stream_read_on_others(haze, frames):
             assert np.array_equal(ref[name], got[name]), name
         for x, y in zip(arrs_ref, arrs):
             assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+
+
+def test_many_calls_over_streams(haze):
+    # more calls than the 64 completion events the context keeps in its ring:
+    # issuing a call's event waits for the one 64 calls back, and older calls
+    # count as complete; outputs still match a serial run bit for bit
+    wl = W.make_small(seed=40, n=4000, width=24, height=16, nviews=1)
+    parts = haze.upload_particles(wl.particles)
+    torch.cuda.synchronize()
+    nframes = 90
+    print(f"case streams: {nframes} small frames over three streams", flush=True)
+    with haze.Context(0) as ctx:
+        ref = _run(haze, ctx, [wl], [parts], [torch.cuda.current_stream()])[0]
+        streams = [torch.cuda.Stream() for _ in range(3)]
+        outs = [haze.alloc_outputs(_nrays(wl)) for _ in range(nframes)]
+        torch.cuda.synchronize()
+        for k in range(nframes):
+            with torch.cuda.stream(streams[k % 3]):
+                f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+                ctx.trace_views(f, wl.views, wl.step_adaptive, out=outs[k])
+                f.release()
+        torch.cuda.synchronize()
+    for k in range(nframes):
+        got = _bits(outs[k])
+        for name in ref:
+            assert np.array_equal(ref[name], got[name]), (k, name)
+
+
+def test_profile_select(haze):
+    wl = W.make_small(seed=41, n=3000)
+    parts = haze.upload_particles(wl.particles)
+    with haze.Context(0) as ctx:
+        with pytest.raises(haze.HazeError) as e:
+            ctx.profile_select("splat,nonsense")
+        assert e.value.status == haze.E_INVALID
+        ctx.profile_select("splat")
+        ctx.profile_enable(True)
+        f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h)
+        ctx.trace_views(f, wl.views, wl.step_adaptive)
+        torch.cuda.synchronize()
+        ctx.profile_enable(False)
+        ms, n = ctx.profile_read("splat")
+        assert n == 1 and ms > 0.0
+        for g in ("cell_list", "grad_pack", "raygen", "march"):
+            assert ctx.profile_read(g)[1] == 0, g
+        ctx.profile_select(None)
+        ctx.profile_enable(True)
+        ctx.trace_views(f, wl.views, wl.step_adaptive)
+        torch.cuda.synchronize()
+        ctx.profile_enable(False)
+        assert ctx.profile_read("march")[1] == 1 and ctx.profile_read("raygen")[1] == 1
+        f.release()
