@@ -254,6 +254,8 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving run (0: skip)")
     ap.add_argument("--serve-frames", type=int, default=60)
     ap.add_argument("--no-membench", action="store_true")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the two-stream leg (whose splats overlap marches), e.g. under a kernel-trace profiler")
     ap.add_argument("--splat", default="gather", choices=["gather", "scatter"])
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
@@ -336,9 +338,11 @@ def main(argv=None):
             f = ctx.splat_index_field(parts, wl.grid, wl.k_gd, wl.h, dtype=args.dtype, store_scale=scale)
             ctx.trace_views(f, wl.views, st_a, out=out_pipe[k])
             f.release()
-    out_pipe = [haze.alloc_outputs(wl.nrays), haze.alloc_outputs(wl.nrays)]
-    pipe_ms = pipelined(ctx, torch, step_on, args.steps, args.warmup)
-    log(f"bench: pipelined (two streams, splat of frame i+1 under trace of frame i): {pipe_ms:.3f} ms/frame")
+    pipe_ms = None
+    if not args.no_pipelined:
+        out_pipe = [haze.alloc_outputs(wl.nrays), haze.alloc_outputs(wl.nrays)]
+        pipe_ms = pipelined(ctx, torch, step_on, args.steps, args.warmup)
+        log(f"bench: pipelined (two streams, splat of frame i+1 under trace of frame i): {pipe_ms:.3f} ms/frame")
     achievable = None
     if not args.no_membench:
         fb = wl.grid.nvox * (16 if args.dtype == "f32" else 8)
@@ -418,8 +422,9 @@ def main(argv=None):
         "splat_pairs": pairs,
         "roofline": roofline,
         "rooflines": {"k_splat": splat_roof, "k_march": march_roof},
-        "pipelined": {"ms_per_frame": pipe_ms, "rays_per_s": nrays / (pipe_ms * 1e-3),
-                      "note": "two streams: the splat of frame i+1 overlaps the trace of frame i"},
+        "pipelined": None if pipe_ms is None else {
+            "ms_per_frame": pipe_ms, "rays_per_s": nrays / (pipe_ms * 1e-3),
+            "note": "two streams: the splat of frame i+1 overlaps the trace of frame i"},
         "achievable_bandwidth": achievable,
         "serving": None,
         "cpu_baseline": None,
