@@ -14,9 +14,9 @@ struct KTimer {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
-// Completion ticket of a library call: the call's place in the context's
+// Completion mark of a library call: the call's place in the context's
 // numbering and the stream its work went to (seq 0: no call).
-struct Ticket {
+struct CallMark {
     uint64_t seq = 0;
     hipStream_t stream = nullptr;
 };

@@ -76,23 +76,23 @@ extern "C" const char *hz_last_error(void) { return g_err.c_str(); }
 // context, ledger and scratch
 // ---------------------------------------------------------------------------
 
-// A device buffer reused across calls.  `last` is the ticket of the call that
+// A device buffer reused across calls.  `last` is the mark of the call that
 // used it last: a reuse on another stream, or freeing it, waits for that.
 struct Scratch {
     void *ptr = nullptr;
     size_t cap = 0;
-    Ticket last;
+    CallMark last;
     bool clean = false;   // holds what its kernels expect on entry (new memory: no)
 };
 
 struct PinnedSlot {
     void *host = nullptr;
     size_t cap = 0;
-    Ticket last;
+    CallMark last;
 };
 
-// Events of the completion tickets (a ring; see ticket_issue).
-constexpr uint64_t kTicketRing = 64;
+// Events of the completion marks (a ring; see mark_issue).
+constexpr uint64_t kMarkRing = 64;
 
 struct hz_field {
     hz_ctx *ctx = nullptr;
@@ -101,8 +101,8 @@ struct hz_field {
     hz_grid grid{};
     hz_dtype dtype = HZ_F32;
     float store_scale = 1.0f;
-    Ticket made;                 // the call that wrote the field
-    std::vector<Ticket> uses;    // the latest call on each stream that touched it
+    CallMark made;                 // the call that wrote the field
+    std::vector<CallMark> uses;    // the latest call on each stream that touched it
     std::mutex mu;
 };
 
@@ -122,9 +122,9 @@ struct hz_ctx {
     int counter_set = 0;
     std::vector<PinnedSlot> pinned;
     size_t pinned_next = 0;
-    hipEvent_t tickets[kTicketRing] = {};
-    uint64_t ticket_next = 1;
-    std::mutex ticket_mu;
+    hipEvent_t marks[kMarkRing] = {};
+    uint64_t mark_next = 1;
+    std::mutex mark_mu;
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
     int march_bpc_scene[2][3] = {};      // by board mode (outer / inner) and dtype
     // march tuning (hz_ctx_tune)
@@ -138,7 +138,7 @@ struct hz_ctx {
     struct PoolBlock {
         void *ptr;
         size_t bytes;
-        std::vector<Ticket> uses;   // the block's last use on each stream
+        std::vector<CallMark> uses;   // the block's last use on each stream
     };
     std::vector<PoolBlock> pool;
     std::mutex pool_mu;
@@ -214,64 +214,64 @@ int ctx_num_cus(const hz_ctx *c) { return c->num_cus; }
 }  // namespace haze
 
 // ---------------------------------------------------------------------------
-// completion tickets
+// completion marks
 // ---------------------------------------------------------------------------
 // Each call that enqueues work records ONE event after its last launch, its
-// ticket, and stamps every buffer and field it used with it.  A later call
-// orders itself after a ticket only when it runs on another stream or must
+// mark, and stamps every buffer and field it used with it.  A later call
+// orders itself after a mark only when it runs on another stream or must
 // free the memory; on the same stream the order is already there.  (An event
 // record is a marker packet that costs the stream microseconds, so one per
-// call rather than one per buffer.)  The events form a ring: issuing ticket q
-// first waits for ticket q - kTicketRing, so a ticket whose event has been
+// call rather than one per buffer.)  The events form a ring: issuing mark q
+// first waits for mark q - kMarkRing, so a mark whose event has been
 // recorded again is known to be complete.
-static hz_status ticket_issue(hz_ctx *c, hipStream_t s, Ticket *out)
+static hz_status mark_issue(hz_ctx *c, hipStream_t s, CallMark *out)
 {
-    std::lock_guard<std::mutex> g(c->ticket_mu);
-    const uint64_t q = c->ticket_next;
-    hipEvent_t &e = c->tickets[q % kTicketRing];
+    std::lock_guard<std::mutex> g(c->mark_mu);
+    const uint64_t q = c->mark_next;
+    hipEvent_t &e = c->marks[q % kMarkRing];
     if (!e)
         HZ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     else
         HZ_HIP(hipEventSynchronize(e), "hipEventSynchronize");
     HZ_HIP(hipEventRecord(e, s), "hipEventRecord");
-    c->ticket_next = q + 1;
-    *out = Ticket{q, s};
+    c->mark_next = q + 1;
+    *out = CallMark{q, s};
     return HZ_OK;
 }
 
-// The event still holding ticket t, or null when t is known to be complete.
-static hipEvent_t ticket_event_locked(hz_ctx *c, const Ticket &t)
+// The event still holding mark t, or null when t is known to be complete.
+static hipEvent_t mark_event_locked(hz_ctx *c, const CallMark &t)
 {
-    if (t.seq == 0 || t.seq + kTicketRing < c->ticket_next) return nullptr;
-    return c->tickets[t.seq % kTicketRing];
+    if (t.seq == 0 || t.seq + kMarkRing < c->mark_next) return nullptr;
+    return c->marks[t.seq % kMarkRing];
 }
 
-// Order `stream` after ticket t.
-static hz_status ticket_wait(hz_ctx *c, const Ticket &t, hipStream_t stream)
+// Order `stream` after mark t.
+static hz_status mark_wait(hz_ctx *c, const CallMark &t, hipStream_t stream)
 {
     if (t.seq == 0 || t.stream == stream) return HZ_OK;
-    std::lock_guard<std::mutex> g(c->ticket_mu);
-    hipEvent_t e = ticket_event_locked(c, t);
+    std::lock_guard<std::mutex> g(c->mark_mu);
+    hipEvent_t e = mark_event_locked(c, t);
     if (e && hipEventQuery(e) != hipSuccess) HZ_HIP(hipStreamWaitEvent(stream, e, 0), "hipStreamWaitEvent");
     return HZ_OK;
 }
 
-// Whether ticket t's work is known to be done (a query; never waits).
-static bool ticket_done(hz_ctx *c, const Ticket &t)
+// Whether mark t's work is known to be done (a query; never waits).
+static bool mark_done(hz_ctx *c, const CallMark &t)
 {
-    std::lock_guard<std::mutex> g(c->ticket_mu);
-    hipEvent_t e = ticket_event_locked(c, t);
+    std::lock_guard<std::mutex> g(c->mark_mu);
+    hipEvent_t e = mark_event_locked(c, t);
     return !e || hipEventQuery(e) == hipSuccess;
 }
 
-// Block the host until ticket t's work is done.  Should the event be recorded
+// Block the host until mark t's work is done.  Should the event be recorded
 // again meanwhile, its issuer has already waited for t.
-static hz_status ticket_sync(hz_ctx *c, const Ticket &t)
+static hz_status mark_sync(hz_ctx *c, const CallMark &t)
 {
     hipEvent_t e;
     {
-        std::lock_guard<std::mutex> g(c->ticket_mu);
-        e = ticket_event_locked(c, t);
+        std::lock_guard<std::mutex> g(c->mark_mu);
+        e = mark_event_locked(c, t);
     }
     if (e) HZ_HIP(hipEventSynchronize(e), "hipEventSynchronize");
     return HZ_OK;
@@ -282,7 +282,7 @@ static hz_status ticket_sync(hz_ctx *c, const Ticket &t)
 static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_t stream)
 {
     if (s.cap < bytes) {
-        hz_status st = ticket_sync(c, s.last);
+        hz_status st = mark_sync(c, s.last);
         if (st != HZ_OK) return st;
         if (s.ptr) {
             ctx_free(c, s.ptr, s.cap);
@@ -297,12 +297,12 @@ static hz_status scratch_acquire(hz_ctx *c, Scratch &s, size_t bytes, hipStream_
         s.cap = want;
         return HZ_OK;
     }
-    return ticket_wait(c, s.last, stream);
+    return mark_wait(c, s.last, stream);
 }
 
 static void scratch_free(hz_ctx *c, Scratch &s)
 {
-    (void)ticket_sync(c, s.last);
+    (void)mark_sync(c, s.last);
     if (s.ptr) ctx_free(c, s.ptr, s.cap);
     s = Scratch{};
 }
@@ -338,12 +338,12 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
 
 static void field_destroy(hz_field *f)
 {
-    for (const Ticket &t : f->uses) (void)ticket_sync(f->ctx, t);
+    for (const CallMark &t : f->uses) (void)mark_sync(f->ctx, t);
     if (f->data) ctx_free(f->ctx, f->data, f->bytes);
     delete f;
 }
 
-// Return a field's memory to the context pool; its last ticket orders any
+// Return a field's memory to the context pool; its latest uses order any
 // reuse after the work that read it, so releasing never blocks the host.
 static void field_recycle(hz_field *f)
 {
@@ -368,7 +368,7 @@ static void pool_trim(hz_ctx *c, size_t need)
     while (!c->pool.empty() && c->used.load() + need > c->budget) {
         hz_ctx::PoolBlock b = c->pool.back();
         c->pool.pop_back();
-        for (const Ticket &t : b.uses) (void)ticket_sync(c, t);
+        for (const CallMark &t : b.uses) (void)mark_sync(c, t);
         ctx_free(c, b.ptr, b.bytes);
     }
 }
@@ -508,10 +508,10 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
                        &c->hits, &c->bins, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
-        (void)ticket_sync(c, p.last);
+        (void)mark_sync(c, p.last);
         if (p.host) (void)hipHostFree(p.host);
     }
-    for (hipEvent_t e : c->tickets)
+    for (hipEvent_t e : c->marks)
         if (e) (void)hipEventDestroy(e);
     delete c;
 }
@@ -597,7 +597,7 @@ static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale
         for (size_t i = 0; i < c->pool.size() && pick < 0; ++i) {
             if (c->pool[i].bytes != f->bytes) continue;
             bool idle = true;
-            for (const Ticket &t : c->pool[i].uses) idle = idle && (t.stream == s || ticket_done(c, t));
+            for (const CallMark &t : c->pool[i].uses) idle = idle && (t.stream == s || mark_done(c, t));
             if (idle) pick = (long)i;
             busy = busy || !idle;
         }
@@ -613,8 +613,8 @@ static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale
         }
     }
     if (f->data) {
-        for (const Ticket &t : f->uses) {
-            hz_status st = ticket_wait(c, t, s);
+        for (const CallMark &t : f->uses) {
+            hz_status st = mark_wait(c, t, s);
             if (st != HZ_OK) {
                 field_destroy(f);
                 return st;
@@ -633,19 +633,19 @@ static hz_status new_field(hz_ctx *c, const hz_grid *g, hz_dtype dt, float scale
     return HZ_OK;
 }
 
-// The call with ticket t wrote the field; it ran after every earlier use.
-static void field_mark_made(hz_field *f, const Ticket &t)
+// The call with mark t wrote the field; it ran after every earlier use.
+static void field_mark_made(hz_field *f, const CallMark &t)
 {
     std::lock_guard<std::mutex> g(f->mu);
     f->made = t;
     f->uses.assign(1, t);
 }
 
-// The call with ticket t read the field.
-static void field_mark_used(hz_field *f, const Ticket &t)
+// The call with mark t read the field.
+static void field_mark_used(hz_field *f, const CallMark &t)
 {
     std::lock_guard<std::mutex> g(f->mu);
-    for (Ticket &u : f->uses)
+    for (CallMark &u : f->uses)
         if (u.stream == t.stream) {
             u = t;
             return;
@@ -656,12 +656,12 @@ static void field_mark_used(hz_field *f, const Ticket &t)
 // Order a read of the field on `s` after the call that wrote it.
 static hz_status field_order_read(hz_ctx *c, hz_field *f, hipStream_t s)
 {
-    Ticket m;
+    CallMark m;
     {
         std::lock_guard<std::mutex> g(f->mu);
         m = f->made;
     }
-    return ticket_wait(c, m, s);
+    return mark_wait(c, m, s);
 }
 
 static void register_field(hz_ctx *c, hz_field *f)
@@ -799,8 +799,8 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         field_destroy(f);
         return st;
     }
-    Ticket done;
-    st = ticket_issue(c, s, &done);
+    CallMark done;
+    st = mark_issue(c, s, &done);
     if (st != HZ_OK) {
         field_destroy(f);
         return st;
@@ -827,8 +827,8 @@ extern "C" hz_status hz_index_field_from_grid(hz_ctx *c, const float *dn, const 
     st = new_field(c, g, dtype, store_scale, s, &f);
     if (st != HZ_OK) return st;
     st = pack_field(c, dn, g, f, s);
-    Ticket done;
-    if (st == HZ_OK) st = ticket_issue(c, s, &done);
+    CallMark done;
+    if (st == HZ_OK) st = mark_issue(c, s, &done);
     if (st != HZ_OK) {
         field_destroy(f);
         return st;
@@ -851,8 +851,8 @@ extern "C" hz_status hz_field_read(hz_ctx *c, const hz_field *fc, float *dn, flo
     hz_status st = field_order_read(c, f, s);
     if (st != HZ_OK) return st;
     HZ_HIP(launch_field_unpack((int)f->dtype, f->data, nv, 1.0f / f->store_scale, dn, gx, gy, gz, s), "unpack launch");
-    Ticket done;
-    st = ticket_issue(c, s, &done);
+    CallMark done;
+    st = mark_issue(c, s, &done);
     if (st == HZ_OK) field_mark_used(f, done);
     return st;
 }
@@ -1001,12 +1001,12 @@ void make_trace_step(const hz_step &st, const hz_grid &g, TraceStep *S)
 }  // namespace haze
 
 // Copy `bytes` from host to device through a pinned staging slot; the caller
-// stamps *slot with its call's ticket.
+// stamps *slot with its call's mark.
 static hz_status staged_copy(hz_ctx *c, void *dst, const void *src, size_t bytes, hipStream_t s, PinnedSlot **slot)
 {
     PinnedSlot &p = c->pinned[c->pinned_next];
     c->pinned_next = (c->pinned_next + 1) % c->pinned.size();
-    hz_status st = ticket_sync(c, p.last);
+    hz_status st = mark_sync(c, p.last);
     if (st != HZ_OK) return st;
     if (p.cap < bytes) {
         if (p.host) (void)hipHostFree(p.host);
@@ -1187,8 +1187,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     prof_commit(c, "march", t1);
     c->counter_set = 1 - c->counter_set;
     c->counters.clean = true;
-    Ticket done;
-    st = ticket_issue(c, s, &done);
+    CallMark done;
+    st = mark_issue(c, s, &done);
     if (st != HZ_OK) return st;
     for (Scratch *b : {&c->jobs, &c->hits, &c->bins, &c->counters}) b->last = done;
     staging->last = done;
@@ -1222,8 +1222,8 @@ hz_dtype field_dtype(const hz_field *f) { return f->dtype; }
 float field_scale(const hz_field *f) { return f->store_scale; }
 const void *field_data(const hz_field *f) { return f->data; }
 hz_ctx *field_ctx(const hz_field *f) { return f->ctx; }
-hz_status ctx_ticket(hz_ctx *c, hipStream_t s, Ticket *out) { return ticket_issue(c, s, out); }
-void field_use(hz_field *f, const Ticket &t) { field_mark_used(f, t); }
+hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out) { return mark_issue(c, s, out); }
+void field_use(hz_field *f, const CallMark &t) { field_mark_used(f, t); }
 hz_status field_ready(hz_field *f, hipStream_t s) { return field_order_read(f->ctx, f, s); }
 int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
 KTimer profile_timer(hz_ctx *c, const char *name) { return prof_timer(c, name); }

@@ -23,8 +23,8 @@ float field_scale(const hz_field *f);
 const void *field_data(const hz_field *f);
 hz_ctx *field_ctx(const hz_field *f);
 hz_status field_ready(hz_field *f, hipStream_t s);       // order a read on s after the field's producer
-void field_use(hz_field *f, const Ticket &t);            // a read by the call with ticket t
-hz_status ctx_ticket(hz_ctx *c, hipStream_t s, Ticket *out);
+void field_use(hz_field *f, const CallMark &t);            // a read by the call with mark t
+hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out);
 int march_blocks(hz_ctx *c, int dt);
 KTimer profile_timer(hz_ctx *c, const char *name);
 void profile_commit(hz_ctx *c, const char *name, const KTimer &t);

@@ -207,8 +207,8 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     sl.counters_clean = true;
     profile_commit(S->ctx, "serve_batch", t);
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
-    Ticket done;
-    hz_status st = ctx_ticket(S->ctx, sl.stream, &done);
+    CallMark done;
+    hz_status st = ctx_mark(S->ctx, sl.stream, &done);
     if (st != HZ_OK) return st;
     for (Request *r : batch) {
         field_use(r->field, done);
