@@ -293,6 +293,29 @@ def test_grid_limits_rejected(ctx, haze):
         assert e.value.status == haze.E_INVALID and "65535" in str(e.value)
 
 
+def test_grid_axis_at_limit(ctx, haze):
+    # 65535 voxels along one axis (the largest accepted), a few along the
+    # others; the long axis spans 0.5 m, so that float32 coordinates of voxel
+    # centres and particles (~ulp 6e-8 m) stay far below the 8 mm support
+    rng = np.random.default_rng(11)
+    n = 3000
+    lo, hi = (0.0, 0.0, 0.0), (0.5, 0.01, 0.012)
+    pos = np.asarray(lo) + rng.random((n, 3)) * (np.asarray(hi) - np.asarray(lo))
+    p = W.Particles(*(pos[:, a].astype(np.float32) for a in range(3)), m=rng.uniform(0.5, 1.5, n).astype(np.float32))
+    for res in ((65535, 2, 3), (3, 2, 65535)):
+        lo_r = lo if res[0] > 3 else (0.0, 0.0, 0.0)
+        hi_r = hi if res[0] > 3 else (0.012, 0.01, 0.5)
+        pts = p if res[0] > 3 else W.Particles(p.z.copy(), p.y, p.x.copy(), m=p.m)
+        grid = W.make_grid(lo_r, hi_r, res)
+        wl = W.Workload("axis-limit", pts, grid, 2.26e-4, 0.004, [], None, None)
+        field, md = _splat_both(ctx, haze, wl)
+        dn, gx, gy, gz = _field_np(ctx, field)
+        ref = md.arrays
+        assert np.count_nonzero(ref[0]) > 1000
+        assert_field_match(dn, (gx, gy, gz), ref[0], ref[1:], grid.spacing, f"axis limit res={res}")
+        field.release()
+
+
 def test_field_from_grid_linear_and_catenary(ctx, haze):
     # a linear delta-n grid: the GPU gradient is exact up to rounding and the
     # rays follow the oracle's (grid-exact) catenary replica
