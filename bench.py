@@ -12,8 +12,8 @@ seeded plumes), 128^3 FP32 grid, one 1280x720 view, adaptive step with
 theta_max = 0.003 and h_max = 1 voxel; the fixed-step trace (0.25 voxel) is
 timed the same way for the adaptive-vs-uniform comparison.
 
-Prints one JSON line (rank 0).  `--gpus N` with N > 1 is refused: this build
-runs on one GPU.
+Prints one JSON line (rank 0).  `--gpus N` with N > 1 is refused: the library
+and this benchmark run on one GPU.
 """
 from __future__ import annotations
 
@@ -263,8 +263,8 @@ def main(argv=None):
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              f"the path shards by views/pixel tiles with the field replicated, see the design notes",
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); on several "
+              f"GPUs the path would split views or pixel tiles with the field replicated on each",
               file=sys.stderr)
         return 2
 

@@ -56,7 +56,7 @@ typedef enum {
     HZ_E_BUDGET = -3,       /* the request can never fit the context's HBM budget */
     HZ_E_DEVICE = -4,       /* no usable GPU, or a HIP runtime/device error */
     HZ_E_NOTFOUND = -5,     /* unknown ticket */
-    HZ_E_UNSUPPORTED = -6   /* valid but not supported by this build */
+    HZ_E_UNSUPPORTED = -6   /* valid but not supported by the library */
 } hz_status;
 
 /* Storage type of the index field.  Integration is always float32. */
