@@ -100,7 +100,7 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  * method and brick depth change only how delta_n is rounded (all meet the same
  * accuracy and each is bitwise repeatable):
  *   "march.refill_min"     refill a wave once this many of its 64 lanes are
- *                          idle, 1..64 (default 16)
+ *                          idle, 1..64 (default 32)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
  *   "splat.method"         0 or 1: gather (one workgroup per 8x8xBZ voxel

@@ -128,7 +128,7 @@ struct hz_ctx {
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
     int march_bpc_scene[2][3] = {};      // by board mode (outer / inner) and dtype
     // march tuning (hz_ctx_tune)
-    int32_t refill_min = 16;
+    int32_t refill_min = 32;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8

@@ -194,7 +194,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.inv_len_bin = length_bin_scale(field_grid(head->field));
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
     make_trace_step(head->step, field_grid(head->field), &L.step);
-    L.refill_min = 16;
+    L.refill_min = 32;
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
     const KTimer t = profile_timer(S->ctx, "serve_batch");

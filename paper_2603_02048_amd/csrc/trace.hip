@@ -532,8 +532,21 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
     // counter past the static range, fetched one batch ahead (the atomic's
     // latency hides behind the march).  Each wave keeps its reserve
     // [next, end) of hit indices.
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    // With F32 samples (128 B per step) and more rays than the resident waves
+    // hold (so lanes are refilled anyway), two thirds of the waves march
+    // faster than all of them (fewer gathers in flight per CU: 4 instead of 6
+    // waves per SIMD, ~5% less time on 8 views of 1280x720).  Every third
+    // workgroup then exits at once, which leaves each CU two thirds of its
+    // workgroups however they were placed, and the rest are renumbered
+    // densely.  With fewer rays, every wave keeps its static batch.
+    uint32_t blk = blockIdx.x, nblk = gridDim.x;
+    if (DT == DT_F32 && SCENE != 2 && ((nh + 63u) >> 6) > nblk * (blockDim.x >> 6)) {
+        if (blk % 3u == 2u) return;
+        blk = 2u * (blk / 3u) + blk % 3u;
+        nblk = 2u * (nblk / 3u) + min(nblk % 3u, 2u);
+    }
+    const uint32_t nwaves = nblk * (blockDim.x >> 6);
+    const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blk * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const uint32_t sb = 64u;
     const uint32_t dyn0 = nwaves * sb;
     uint32_t next = min(wave_id * sb, nh);
