@@ -282,6 +282,18 @@ def test_trace_edge_cases(ctx, haze):
     field.release()
 
 
+def test_tune_keys_checked(ctx, haze):
+    for key, bad in (("march.refill_min", 0), ("march.refill_min", 65), ("march.blocks_per_cu", -1),
+                     ("march.blocks_per_cu", 65), ("splat.method", 3), ("splat.brick_z", 5), ("splat.brick_z", 16),
+                     ("no.such.key", 1)):
+        with pytest.raises(haze.HazeError) as e:
+            ctx.tune(key, bad)
+        assert e.value.status == haze.E_INVALID, (key, bad)
+    for key, good in (("march.refill_min", 32), ("march.blocks_per_cu", 0), ("splat.method", 0),
+                      ("splat.brick_z", 8), ("splat.brick_z", 0)):
+        ctx.tune(key, good)
+
+
 def test_grid_limits_rejected(ctx, haze):
     # each axis holds 2 to 65535 voxels; nothing is launched for a bad grid
     wl = W.make_small(seed=6, n=500)
