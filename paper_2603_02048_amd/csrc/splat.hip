@@ -324,6 +324,30 @@ __device__ __forceinline__ void splat_row(const SplatParams &P, float cx, float 
     if (s < s1) splat_candidate<V0, V1>(P, cx, cy, cz, parts[s], acc);
 }
 
+// splat_row over planes 0..v1 (none when v1 < 0), v1 wave-uniform.
+template <int V1>
+__device__ __forceinline__ void splat_row_upto(int v1, const SplatParams &P, float cx, float cy, const float *cz,
+                                               const float4 *__restrict__ parts, uint32_t s0, uint32_t s1,
+                                               float *acc)
+{
+    if constexpr (V1 >= 0) {
+        if (v1 == V1) splat_row<0, V1>(P, cx, cy, cz, parts, s0, s1, acc);
+        else splat_row_upto<V1 - 1>(v1, P, cx, cy, cz, parts, s0, s1, acc);
+    }
+}
+
+// splat_row over planes v0..BZ-1 (none when v0 >= BZ), 1 <= v0, v0 wave-uniform.
+template <int BZ, int V0 = 1>
+__device__ __forceinline__ void splat_row_from(int v0, const SplatParams &P, float cx, float cy, const float *cz,
+                                               const float4 *__restrict__ parts, uint32_t s0, uint32_t s1,
+                                               float *acc)
+{
+    if constexpr (V0 < BZ) {
+        if (v0 == V0) splat_row<V0, BZ - 1>(P, cx, cy, cz, parts, s0, s1, acc);
+        else splat_row_from<BZ, V0 + 1>(v0, P, cx, cy, cz, parts, s0, s1, acc);
+    }
+}
+
 // One workgroup per brick of 8 x 8 x BZ voxels (BZ = 4 or 8); in each of its
 // four waves, lane (lane & 7, lane >> 3) owns the column of BZ voxels along z.  The brick's
 // cell-list rows near it (each row's x-range cut to the support circle) are
@@ -409,37 +433,27 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
         const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
         const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
         const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
-        if (BZ == 4) {
-            // The row's particles lie in the z-cell [zl, zl + cell]: voxel
-            // planes farther than R from it (a margin of 0.1% of R covers the
-            // rounding of cell ids) are skipped for the whole row, through a
-            // copy of the loop specialised to the planes in reach (on config 2,
-            // 0.6 of the 4 planes per candidate).
-            const float Rm = 1.001f * R;
-            const float zlo = zl - Rm, zhi = zl + cg.cell + Rm;
-            int below = 0, above = 0;
+        // The row's particles lie in the z-cell [zl, zl + cell]: voxel planes
+        // farther than R from it (a margin of 0.1% of R covers the rounding of
+        // cell ids) are skipped for the whole row, through a copy of the loop
+        // specialised to the planes in reach (0.6 of 4 planes per candidate at
+        // 128^3 with 2:1 voxels, 1.4 of 8 at 256^3).  When the reach (cell + 2R)
+        // is longer than the brick, only one end is ever cut; a row with both
+        // ends cut takes the full loop, whose per-voxel test rejects the rest.
+        const float Rm = 1.001f * R;
+        const float zlo = zl - Rm, zhi = zl + cg.cell + Rm;
+        int below = 0, above = 0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                below += cz[v] <= zlo;
-                above += cz[v] >= zhi;
-            }
-            const int v0 = __builtin_amdgcn_readfirstlane(below), v1 = __builtin_amdgcn_readfirstlane(3 - above);
-            switch (v0 * 4 + v1) {
-            case 0: splat_row<0, 0>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 1: splat_row<0, 1>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 2: splat_row<0, 2>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 3: splat_row<0, 3>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 5: splat_row<1, 1>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 6: splat_row<1, 2>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 7: splat_row<1, 3>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 10: splat_row<2, 2>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 11: splat_row<2, 3>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            case 15: splat_row<3, 3>(P, cx, cy, cz, parts, s0, s1, acc); break;
-            default: break;   // no plane in reach
-            }
-        } else {
-            splat_row<0, BZ - 1>(P, cx, cy, cz, parts, s0, s1, acc);
+        for (int v = 0; v < BZ; ++v) {
+            below += cz[v] <= zlo;
+            above += cz[v] >= zhi;
         }
+        const int v0 = __builtin_amdgcn_readfirstlane(below);
+        const int v1 = __builtin_amdgcn_readfirstlane(BZ - 1 - above);
+        if (v0 > v1) continue;   // no plane in reach
+        if (v0 == 0) splat_row_upto<BZ - 1>(v1, P, cx, cy, cz, parts, s0, s1, acc);
+        else if (v1 == BZ - 1) splat_row_from<BZ>(v0, P, cx, cy, cz, parts, s0, s1, acc);
+        else splat_row<0, BZ - 1>(P, cx, cy, cz, parts, s0, s1, acc);
     }
     if (wave > 0) {
 #pragma unroll
