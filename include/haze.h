@@ -110,7 +110,8 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *                          tile axis, HZ_E_UNSUPPORTED beyond); both are
  *                          bitwise repeatable
  *   "splat.brick_z"        gather brick depth BZ: 4 or 8 voxels, 0 = the one
- *                          that makes the brick closer to a cube (default 0)
+ *                          that brings the brick closer to twice as deep as
+ *                          wide (default 0)
  * Errors: HZ_E_INVALID (unknown key or value out of range). */
 hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 

@@ -728,12 +728,13 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     }
     sp.nbx = (g->res[0] + SPLAT_BX - 1) / SPLAT_BX;
     sp.nby = (g->res[1] + SPLAT_BY - 1) / SPLAT_BY;
-    // brick depth: the one of 4 or 8 voxels that makes the brick closer to a
-    // cube (8 when the z spacing is below sqrt(2) times the x-y spacing)
+    // brick depth: the one of 4 or 8 voxels that brings the brick closer to
+    // twice as deep as wide, the shape measured fastest with the per-row plane
+    // skip (8 unless the z spacing exceeds 2 sqrt(2) times the x-y spacing)
     if (c->splat_brick_z == 4 || c->splat_brick_z == 8)
         sp.bz = c->splat_brick_z;
     else
-        sp.bz = (double)sp.sp[2] < 1.41421356 * 0.5 * ((double)sp.sp[0] + (double)sp.sp[1]) ? 8 : 4;
+        sp.bz = (double)sp.sp[2] <= 2.82842712 * 0.5 * ((double)sp.sp[0] + (double)sp.sp[1]) ? 8 : 4;
     sp.nbz = (g->res[2] + sp.bz - 1) / sp.bz;
     sp.h = prm->h;
     sp.inv_h = (float)(1.0 / h);
