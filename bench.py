@@ -349,8 +349,15 @@ def main(argv=None):
         achievable = {"hbm_read_GBps": ctx.membench(4 << 30, 5),
                       "field_sized_read_GBps": ctx.membench(fb, 50),
                       "field_bytes": fb}
+        # the marcher's own pattern with no arithmetic: as many straight rays as
+        # enter the volume, each taking the mean number of steps of the adaptive trace
+        hits = max(1, res["adaptive"]["hits"])
+        walk = max(1, round(res["adaptive"]["steps"] / hits))
+        achievable["field_sized_gather_GBps"] = ctx.membench_gather(wl.grid.res, fb // wl.grid.nvox, hits, walk, 20)
+        achievable["gather_walk"] = {"walkers": hits, "steps": walk}
         log(f"bench: achievable read bandwidth: 4 GiB buffer {achievable['hbm_read_GBps']:.0f} GB/s, "
-            f"field-sized ({fb >> 20} MiB) {achievable['field_sized_read_GBps']:.0f} GB/s")
+            f"field-sized ({fb >> 20} MiB) {achievable['field_sized_read_GBps']:.0f} GB/s, "
+            f"marcher-pattern gathers ({hits} rays x {walk} steps) {achievable['field_sized_gather_GBps']:.0f} GB/s")
 
     A, U = res["adaptive"], res["uniform"]
     rays_s = nrays / (A["ms"] * 1e-3)
@@ -372,6 +379,8 @@ def main(argv=None):
     if achievable:
         march_roof["achievable_GBps_field_sized"] = achievable["field_sized_read_GBps"]
         march_roof["frac_of_achievable"] = march_gbs / achievable["field_sized_read_GBps"]
+        march_roof["achievable_GBps_gather"] = achievable["field_sized_gather_GBps"]
+        march_roof["frac_of_achievable_gather"] = march_gbs / achievable["field_sized_gather_GBps"]
     pairs = None
     splat_roof = None
     if not args.no_pairs:

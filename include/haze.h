@@ -138,6 +138,20 @@ hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int
  * HZ_E_NOMEM, HZ_E_DEVICE. */
 hz_status hz_membench(hz_ctx *ctx, uint64_t bytes, int32_t reps, double *read_gbps, void *hip_stream);
 
+/* Achievable gather bandwidth (GB/s) of the tracer's access pattern with no
+ * arithmetic around it: `walkers` straight rays (8 x 8 pixel tiles of one
+ * image, entering the z = 0 face of a res[0] x res[1] x res[2] grid of
+ * `voxel_bytes`-byte voxels, 16 as F32 fields and 8 as F16/BF16 ones) each
+ * take `steps` steps of one voxel, reading the 8 corners of their cell per
+ * step the way the marcher does; counted as walkers x steps x 8 x voxel_bytes
+ * per launch, `reps` timed launches after one warm-up.  Allocates (and frees)
+ * the grid against the budget; synchronises `hip_stream`.
+ * Errors: HZ_E_INVALID (voxel_bytes not 8 or 16, res outside [2, 65535] or a
+ * grid of 2^31 voxels or more, walkers outside [1, 2^26], steps outside
+ * [1, 65536], reps outside [1, 10000]), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_membench_gather(hz_ctx *ctx, const int32_t res[3], int32_t voxel_bytes, int32_t walkers, int32_t steps,
+                             int32_t reps, double *gather_gbps, void *hip_stream);
+
 /* ---------------------------------------------------------------------- */
 /* Index field (paper Sec. 3.3.1, Eqs. 12-13)                             */
 /* ---------------------------------------------------------------------- */

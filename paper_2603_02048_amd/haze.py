@@ -74,7 +74,7 @@ class hz_scene(C.Structure):
 
 
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
-           "hz_profile_select", "hz_profile_read", "hz_membench", "hz_splat_index_field",
+           "hz_profile_select", "hz_profile_read", "hz_membench", "hz_membench_gather", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_trace_scene",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
@@ -98,6 +98,9 @@ def lib():
         L.hz_ctx_tune.argtypes, L.hz_ctx_tune.restype = [P, C.c_char_p, C.c_int64], S
         L.hz_membench.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(C.c_double), P]
         L.hz_membench.restype = S
+        L.hz_membench_gather.argtypes = [P, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                         C.POINTER(C.c_double), P]
+        L.hz_membench_gather.restype = S
         L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
         L.hz_profile_select.argtypes, L.hz_profile_select.restype = [P, C.c_char_p], S
         L.hz_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -258,6 +261,14 @@ class Context:
         g = C.c_double()
         _check(lib().hz_membench(C.c_void_p(self.handle), int(nbytes), int(reps), C.byref(g), _stream(stream)),
                "membench")
+        return g.value
+
+    def membench_gather(self, res, voxel_bytes: int, walkers: int, steps: int, reps: int = 10, stream=None) -> float:
+        """Achievable GB/s of the marcher's 8-corner gathers along straight rays (see hz_membench_gather)."""
+        r = (C.c_int32 * 3)(*[int(v) for v in res])
+        g = C.c_double()
+        _check(lib().hz_membench_gather(C.c_void_p(self.handle), r, int(voxel_bytes), int(walkers), int(steps),
+                                        int(reps), C.byref(g), _stream(stream)), "membench_gather")
         return g.value
 
     def profile_enable(self, enable: bool = True):
