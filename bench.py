@@ -45,20 +45,30 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+def code_digest(path: str) -> str:
+    """SHA-256 of a source file's code: comments dropped, whitespace runs
+    collapsed (so an edit of comments alone keeps the digest)."""
+    import hashlib
+    import re
+    with open(path, encoding="utf-8") as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
+
+
 def measured_traffic(kernel: str, row: str, config: int, dtype: str):
     """HBM/fabric bytes per launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None when
-    the workload differs from the counted one or the kernel's source has
+    the workload differs from the counted one or the kernel's code has
     changed since the counters were taken."""
-    import hashlib
     if config != 2 or dtype != "f32" or not os.path.exists(COUNTERS):
         return None
     with open(COUNTERS) as f:
         c = json.load(f)
     src = KERNEL_SOURCE[kernel]
-    with open(os.path.join(ROOT, src), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != c["source_sha256"].get(src):
-            return None
+    if code_digest(os.path.join(ROOT, src)) != c.get("code_sha256", {}).get(src):
+        return None
     k = c["kernels"][row]
     return {"bytes": k["fetch_bytes"] + k["write_bytes"], "read_bytes": k["fetch_bytes"],
             "write_bytes": k["write_bytes"], "fetch_scale": c["calibration"]["fetch_scale"],

@@ -636,8 +636,8 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 }
             }
         }
-        // The refilled lanes step in the same iteration; the loop has one
-        // back-edge, so loop-carried values need no register copies.
+        // The refilled lanes step in the same iteration: the loop has one
+        // back-edge.
         if (done && __ballot(active) == 0ull) {
             if (fin >= 0) finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
             break;
