@@ -64,11 +64,21 @@ def _default(ctx):
 
 @pytest.mark.parametrize("method", ["gather", "gather8", "scatter"])
 @pytest.mark.parametrize("seed,res,h", [(0, (21, 17, 13), 0.03), (1, (8, 9, 30), 0.05), (2, (2, 3, 2), 0.2),
-                                        (3, (40, 33, 19), 0.02)])
+                                        (3, (40, 33, 19), 0.02),
+                                        # z reach (cell + 4h) shorter than a brick: cell rows whose reach
+                                        # cuts the brick at both ends (full loop) or misses it
+                                        (4, (24, 20, 10), 0.012)])
 def test_splat_parity_small(ctx, haze, seed, res, h, method):
     _use(ctx, method)
     try:
         wl = W.make_small(seed=seed, res=res, h=h, n=6000)
+        if method == "scatter" and seed == 4:
+            # the scatter tile grown by 2h spans more cell rows than it can
+            # list at this h: refused, as documented
+            with pytest.raises(haze.HazeError) as e:
+                ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
+            assert e.value.status == haze.E_UNSUPPORTED
+            return
         field, md = _splat_both(ctx, haze, wl)
         dn, gx, gy, gz = _field_np(ctx, field)
         ref = md.arrays
