@@ -158,7 +158,7 @@ struct TraceLaunch {
 // cleared once by k_trace_init).
 constexpr int kRayBins = 32;
 constexpr int kCounterStride = 64;
-constexpr int kRaygenBlock = 256;
+constexpr int kRaygenBlock = 1024;
 constexpr int kMarchHead = 2 * kRayBins;
 constexpr size_t kCounterSetWords = (size_t)(kMarchHead + 1) * kCounterStride;
 constexpr size_t kCounterBytes = 2 * kCounterSetWords * 4;
