@@ -643,52 +643,69 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
-// A workgroup covers 64 x 4 voxels of one z-slice: grid (ceil(rx/64),
-// ceil(ry/4), rz), so no index division.
+// A workgroup covers 64 x 4 columns of GP_Z voxels along z: grid
+// (ceil(rx/64), ceil(ry/4), ceil(rz/GP_Z)), so no index division.  Walking up
+// the column keeps the z-neighbours in registers (5 loads per voxel, not 7).
+constexpr int GP_Z = 4;
+
+template <int DT>
+__device__ __forceinline__ void store_voxel(void *__restrict__ out, int32_t v, float c, float gx, float gy, float gz,
+                                            float scale)
+{
+    if (DT == DT_F32) {
+        reinterpret_cast<float4 *>(out)[v] = make_float4(c, gx, gy, gz);
+    } else if (DT == DT_F16) {
+        ushort4 h;
+        h.x = __half_as_ushort(__float2half_rn(c * scale));
+        h.y = __half_as_ushort(__float2half_rn(gx * scale));
+        h.z = __half_as_ushort(__float2half_rn(gy * scale));
+        h.w = __half_as_ushort(__float2half_rn(gz * scale));
+        reinterpret_cast<ushort4 *>(out)[v] = h;
+    } else {
+        ushort4 h;
+        h.x = f32_to_bf16_rne(c * scale);
+        h.y = f32_to_bf16_rne(gx * scale);
+        h.z = f32_to_bf16_rne(gy * scale);
+        h.w = f32_to_bf16_rne(gz * scale);
+        reinterpret_cast<ushort4 *>(out)[v] = h;
+    }
+}
+
+// Inside: (f[i+1] - f[i-1]) / (2 d); faces: one-sided first difference.
+__device__ __forceinline__ float central(float fm, float c, float fp, int32_t idx, int32_t n, float inv)
+{
+    if (idx == 0) return (fp - c) * inv;
+    if (idx == n - 1) return (c - fm) * inv;
+    return (fp - fm) * (0.5f * inv);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t rx, int32_t ry, int32_t rz,
                                                    float ix, float iy, float iz, float scale, void *__restrict__ out)
 {
     const int32_t i = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
     const int32_t j = (int32_t)blockIdx.y * 4 + (int32_t)(threadIdx.x >> 6);
-    const int32_t k = (int32_t)blockIdx.z;
+    const int32_t k0 = (int32_t)blockIdx.z * GP_Z;
     if (i >= rx || j >= ry) return;
     // voxel counts are below 2^31 (checked on the host): 32-bit index math
     const int32_t sy = rx, sz = rx * ry;
-    const int32_t v = (k * ry + j) * rx + i;
-    const float c = dn[v];
-    float g[3];
-    {
-        // inside: (f[i+1] - f[i-1]) / (2 d); faces: one-sided first difference
-        const int32_t idx[3] = {i, j, k};
-        const int32_t R[3] = {rx, ry, rz};
-        const int32_t st[3] = {1, sy, sz};
-        const float inv[3] = {ix, iy, iz};
-        for (int a = 0; a < 3; ++a) {
-            if (idx[a] == 0)
-                g[a] = (dn[v + st[a]] - c) * inv[a];
-            else if (idx[a] == R[a] - 1)
-                g[a] = (c - dn[v - st[a]]) * inv[a];
-            else
-                g[a] = (dn[v + st[a]] - dn[v - st[a]]) * (0.5f * inv[a]);
-        }
-    }
-    if (DT == DT_F32) {
-        reinterpret_cast<float4 *>(out)[v] = make_float4(c, g[0], g[1], g[2]);
-    } else if (DT == DT_F16) {
-        ushort4 h;
-        h.x = __half_as_ushort(__float2half_rn(c * scale));
-        h.y = __half_as_ushort(__float2half_rn(g[0] * scale));
-        h.z = __half_as_ushort(__float2half_rn(g[1] * scale));
-        h.w = __half_as_ushort(__float2half_rn(g[2] * scale));
-        reinterpret_cast<ushort4 *>(out)[v] = h;
-    } else {
-        ushort4 h;
-        h.x = f32_to_bf16_rne(c * scale);
-        h.y = f32_to_bf16_rne(g[0] * scale);
-        h.z = f32_to_bf16_rne(g[1] * scale);
-        h.w = f32_to_bf16_rne(g[2] * scale);
-        reinterpret_cast<ushort4 *>(out)[v] = h;
+    int32_t v = (k0 * ry + j) * rx + i;
+    // x and y neighbours (and the z ones, from the column walk) stay inside
+    // the grid: a face uses the one-sided difference
+    const int32_t xm = i > 0 ? -1 : 0, xp = i < rx - 1 ? 1 : 0;
+    const int32_t ym = j > 0 ? -sy : 0, yp = j < ry - 1 ? sy : 0;
+    float zm = k0 > 0 ? dn[v - sz] : 0.0f;
+    float c = dn[v];
+    const int32_t k1 = min(k0 + GP_Z, rz);
+    for (int32_t k = k0; k < k1; ++k) {
+        const float zp = k + 1 < rz ? dn[v + sz] : 0.0f;
+        const float gx = central(dn[v + xm], c, dn[v + xp], i, rx, ix);
+        const float gy = central(dn[v + ym], c, dn[v + yp], j, ry, iy);
+        const float gz = central(zm, c, zp, k, rz, iz);
+        store_voxel<DT>(out, v, c, gx, gy, gz, scale);
+        zm = c;
+        c = zp;
+        v += sz;
     }
 }
 
@@ -801,7 +818,8 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
 hipError_t launch_grad_pack(int dtype, const float *dn, const int32_t res[3], const float inv_sp[3], float scale,
                             void *out, hipStream_t s, const KTimer &t)
 {
-    const dim3 g((unsigned)((res[0] + 63) / 64), (unsigned)((res[1] + 3) / 4), (unsigned)res[2]), b(256);
+    const dim3 g((unsigned)((res[0] + 63) / 64), (unsigned)((res[1] + 3) / 4), (unsigned)((res[2] + GP_Z - 1) / GP_Z)),
+        b(256);
     if (dtype == DT_F32)
         hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
                               inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
