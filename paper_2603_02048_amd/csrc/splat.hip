@@ -297,11 +297,13 @@ __device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, 
             if (r2 < P.support2) {
                 // M4 spline times 4: 4 - 6q^2 + 3q^3 (q < 1), (2 - q)^3 (1 <= q < 2).
                 // With u = 1 - q (in (-1, 1] here) both pieces are
-                // 1 + 3u + 3u^2 + c u^3, c = -3 for u > 0 and 1 otherwise: one
-                // select and three FMAs (the factor 1/4 is in the final scale)
+                // 1 + 3u + 3u^2 + c u^3, c = -3 for u > 0 and 1 otherwise, and
+                // c u = min(u, -3u): a multiply and a min pick the piece (no
+                // compare-and-select, whose mask write stalls the next
+                // instruction), then Horner (the factor 1/4 is in the final scale)
                 const float u = fmaf(-__builtin_amdgcn_sqrtf(r2), P.inv_h, 1.0f);
-                const float c3 = u > 0.0f ? -3.0f : 1.0f;
-                const float w4 = fmaf(fmaf(fmaf(c3, u, 3.0f), u, 3.0f), u, 1.0f);
+                const float cu = fminf(u, -3.0f * u);
+                const float w4 = fmaf(fmaf(3.0f + cu, u, 3.0f), u, 1.0f);
                 acc[v] = fmaf(q.w, w4, acc[v]);
             }
         }
