@@ -75,6 +75,22 @@ def measured_traffic(kernel: str, row: str, config: int, dtype: str):
             "write_scale": c["calibration"]["write_scale"], "source": "profiles/counters_config2_f32.md"}
 
 
+def per_view_steps(out, wl) -> list:
+    """Per view (rays concatenated in view order): rays that enter the volume,
+    their mean and largest step count, and a histogram of their step counts in
+    bins of 32 steps."""
+    steps = out["steps"].cpu().numpy().astype(np.int64)
+    res, o = [], 0
+    for v in wl.views:
+        s = steps[o:o + v.nrays]
+        o += v.nrays
+        s = s[s > 0]
+        hist = np.bincount(s // 32).tolist() if s.size else []
+        res.append({"rays_in_volume": int(s.size), "mean_steps": float(s.mean()) if s.size else 0.0,
+                    "max_steps": int(s.max()) if s.size else 0, "hist32": hist})
+    return res
+
+
 def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat",), live_every: int = 4):
     """ms per step over exactly `steps` steps (host clock between two device
     synchronisations) with the `live` kernel groups timed by their own
@@ -321,7 +337,7 @@ def main(argv=None):
         ms, per, kt = time_steps(ctx, torch, make_step(st), args.steps, args.warmup, kernels)
         steps_total = int(out["steps"].sum().item())
         hits = int((out["steps"] > 0).sum().item())
-        res[name] = dict(ms=ms, per=per, kt=kt, steps=steps_total, hits=hits)
+        res[name] = dict(ms=ms, per=per, kt=kt, steps=steps_total, hits=hits, per_view=per_view_steps(out, wl))
         log(f"bench: {name}: {ms:.3f} ms/step (p50 {np.percentile(per, 50):.3f}, p99 {np.percentile(per, 99):.3f}), "
             f"ray-steps {steps_total}, rays in volume {hits}; kernels " +
             ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in kt.items()))
@@ -429,6 +445,7 @@ def main(argv=None):
         "ray_steps_per_s": A["steps"] / (A["ms"] * 1e-3),
         "latency_ms": {"p50": float(np.percentile(A["per"], 50)), "p99": float(np.percentile(A["per"], 99))},
         "adaptive": {"rays_per_s": rays_s, "ray_steps": A["steps"], "rays_in_volume": A["hits"],
+                     "per_view": A["per_view"],
                      "trace_rays_per_s": nrays / ((avg["raygen"] + avg["march"]) * 1e-3),
                      "trace_ray_steps_per_s": A["steps"] / ((avg["raygen"] + avg["march"]) * 1e-3)},
         "uniform": {"rays_per_s": nrays / (U["ms"] * 1e-3), "ms_per_step": U["ms"], "ray_steps": U["steps"],
