@@ -99,6 +99,9 @@ def lib():
         L.ho_trace_scene.restype = C.c_int
         L.ho_trace_scene.argtypes = [C.POINTER(_Medium), C.POINTER(_View), C.c_int32, P, C.c_int32,
                                      C.POINTER(_Step), P, C.c_int64, P, P, P, P, P, P]
+        L.ho_trace_mesh.restype = C.c_int
+        L.ho_trace_mesh.argtypes = [C.POINTER(_Medium), C.POINTER(_View), C.c_int32, P, C.c_int32,
+                                    C.POINTER(_Step), P, C.c_int64, P, P, P, P, P, P]
         L.ho_trace_rays.restype = C.c_int
         L.ho_trace_rays.argtypes = [C.POINTER(_Medium), C.POINTER(_Step), P, P, C.c_int64, P, P, P, P]
         L.ho_trace_rays_rk4.restype = C.c_int
@@ -301,6 +304,40 @@ def trace_scene(medium: Medium, views, quads, step, ray_ids: Optional[np.ndarray
                               C.byref(_step(step)), None if ids is None else _ptr(ids), n, _ptr(out["disp"]),
                               _ptr(out["exit_pos"]), _ptr(out["exit_dir"]), _ptr(out["steps"]),
                               _ptr(out["status"]), _ptr(out["surface"]))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc}): ray id out of range")
+    return out
+
+
+class _Tri(C.Structure):
+    _fields_ = [("v0", C.c_double * 3), ("e1", C.c_double * 3), ("e2", C.c_double * 3), ("surf", C.c_int32)]
+
+
+def trace_mesh(medium: Medium, views, tris, surfaces, step, ray_ids: Optional[np.ndarray] = None) -> dict:
+    """trace_views with a triangle-mesh scene, every chord and straight segment
+    tested against every triangle: `tris` is (T, 3, 3) vertices (v0, v1, v2)
+    per triangle, `surfaces` (T,) the surface each belongs to.  Adds `surface`
+    per ray: 0 backdrop plane, s + 1 a triangle of surface s, 255 none."""
+    v = np.asarray(tris, np.float64).reshape(-1, 3, 3)
+    sf = np.asarray(surfaces, np.int64).reshape(-1)
+    assert sf.shape[0] == v.shape[0]
+    arr = (_Tri * max(1, v.shape[0]))()
+    for i in range(v.shape[0]):
+        t = arr[i]
+        for a in range(3):
+            t.v0[a] = float(v[i, 0, a])
+            t.e1[a] = float(v[i, 1, a] - v[i, 0, a])
+            t.e2[a] = float(v[i, 2, a] - v[i, 0, a])
+        t.surf = int(sf[i])
+    total = sum(int(vw.width) * int(vw.height) for vw in views)
+    ids = None if ray_ids is None else np.ascontiguousarray(ray_ids, np.int64)
+    n = total if ids is None else int(ids.shape[0])
+    out = dict(disp=np.empty((n, 2)), exit_pos=np.empty((n, 3)), exit_dir=np.empty((n, 3)),
+               steps=np.empty(n, np.int64), status=np.empty(n, np.uint8), surface=np.empty(n, np.uint8))
+    rc = lib().ho_trace_mesh(medium.ref, _views(views), len(views), C.cast(arr, C.c_void_p) if v.shape[0] else None,
+                             v.shape[0], C.byref(_step(step)), None if ids is None else _ptr(ids), n,
+                             _ptr(out["disp"]), _ptr(out["exit_pos"]), _ptr(out["exit_dir"]), _ptr(out["steps"]),
+                             _ptr(out["status"]), _ptr(out["surface"]))
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc}): ray id out of range")
     return out

@@ -16,9 +16,13 @@
  *   - straight rays outside the volume              (Fig. 1 caption)
  *   - image formed only by bending, via intersecting the refracted ray with
  *     the scene                                     (Sec. 3.3.2, last paragraph)
- *   - scene surfaces (planar parallelograms) met anywhere along the ray: before
- *     the volume, on the chord of any step inside it, or after it; the first
- *     one met ends the ray                          (Sec. 3.3.2; Sec. 4.2)
+ *   - scene surfaces (planar parallelograms, or triangle meshes) met anywhere
+ *     along the ray: before the volume, on the chord of any step inside it, or
+ *     after it; the first one met ends the ray       (Sec. 3.3.2; Secs. 4.1-4.2)
+ *     Every chord and straight segment is tested against every surface by
+ *     brute force: the acceleration structure of Sec. 4.1 (a conservative
+ *     shell around the geometry) only decides which exact tests to skip, so
+ *     the oracle has none.
  *
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes):
@@ -88,6 +92,22 @@ typedef struct {
 typedef struct {
     double o[3], ea[3], eb[3];
 } ho_quad;
+
+/* A scene triangle v0 + u e1 + v e2, u, v >= 0, u + v <= 1, seen from either
+ * side; `surf` is the surface (mesh part) it belongs to. */
+typedef struct {
+    double v0[3], e1[3], e2[3];
+    int32_t surf;
+} ho_tri;
+
+/* The surfaces of one trace: quads (surface k is quad k) and triangles
+ * (surface tris[i].surf); a hit reports its surface. */
+typedef struct {
+    const ho_quad *quads;
+    int32_t nq;
+    const ho_tri *tris;
+    int32_t nt;
+} ho_scene;
 
 /* ------------------------------------------------------------------ */
 /* small vector helpers                                               */
@@ -395,44 +415,86 @@ static double quad_side(const ho_quad *q, const double h[3])
     return dot3(r, nrm);
 }
 
-/* First quad met by the straight ray o + t d with t in [0, t_max]; returns its
- * index (or -1) and the parameter t.  Ties go to the lower index. */
-static int cast_quads(const ho_quad *quads, int32_t nq, const double o[3], const double d[3], double t_max,
-                      double *t_hit)
+/* Is the point h, on the plane of triangle t, inside it?  The same Cramer
+ * solve as in_quad, with the triangle's condition u, v >= 0, u + v <= 1. */
+static int in_tri(const ho_tri *t, const double h[3])
+{
+    double nrm[3], r[3] = {h[0] - t->v0[0], h[1] - t->v0[1], h[2] - t->v0[2]}, c[3];
+    cross3(t->e1, t->e2, nrm);
+    double det = dot3(nrm, nrm);
+    cross3(r, t->e2, c);
+    double u = dot3(c, nrm) / det;
+    cross3(t->e1, r, c);
+    double v = dot3(c, nrm) / det;
+    return u >= 0.0 && v >= 0.0 && u + v <= 1.0;
+}
+
+/* (h - v0) . (e1 x e2): the side of the triangle's plane h lies on. */
+static double tri_side(const ho_tri *t, const double h[3])
+{
+    double nrm[3], r[3] = {h[0] - t->v0[0], h[1] - t->v0[1], h[2] - t->v0[2]};
+    cross3(t->e1, t->e2, nrm);
+    return dot3(r, nrm);
+}
+
+/* Surface j of a scene (quads first, then triangles): its plane side value
+ * at h, whether h (on its plane) lies on it, the plane normal, and the
+ * surface id a hit reports. */
+static double surf_side(const ho_scene *sc, int32_t j, const double h[3])
+{
+    return j < sc->nq ? quad_side(&sc->quads[j], h) : tri_side(&sc->tris[j - sc->nq], h);
+}
+static int surf_inside(const ho_scene *sc, int32_t j, const double h[3])
+{
+    return j < sc->nq ? in_quad(&sc->quads[j], h) : in_tri(&sc->tris[j - sc->nq], h);
+}
+static void surf_normal(const ho_scene *sc, int32_t j, double nrm[3])
+{
+    if (j < sc->nq)
+        cross3(sc->quads[j].ea, sc->quads[j].eb, nrm);
+    else
+        cross3(sc->tris[j - sc->nq].e1, sc->tris[j - sc->nq].e2, nrm);
+}
+static int surf_id(const ho_scene *sc, int32_t j) { return j < sc->nq ? j : sc->tris[j - sc->nq].surf; }
+
+/* First surface met by the straight ray o + t d with t in [0, t_max]; returns
+ * its id (or -1) and the parameter t.  Among equal t the one listed first
+ * wins. */
+static int cast_scene(const ho_scene *sc, const double o[3], const double d[3], double t_max, double *t_hit)
 {
     int best = -1;
     double bt = t_max;
-    for (int32_t k = 0; k < nq; ++k) {
+    for (int32_t j = 0; j < sc->nq + sc->nt; ++j) {
         double nrm[3];
-        cross3(quads[k].ea, quads[k].eb, nrm);
+        surf_normal(sc, j, nrm);
         double dn = dot3(d, nrm);
         if (dn == 0.0) continue;
-        double t = -quad_side(&quads[k], o) / dn;
+        double t = -surf_side(sc, j, o) / dn;
         if (!(t >= 0.0) || t > bt || (t == bt && best >= 0)) continue;
         double h[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-        if (!in_quad(&quads[k], h)) continue;
-        best = k;
+        if (!surf_inside(sc, j, h)) continue;
+        best = surf_id(sc, j);
         bt = t;
     }
     *t_hit = bt;
     return best;
 }
 
-/* First quad crossed by the chord a -> b of one step: the side value changes
- * sign, or is zero at b, after being non-zero at a.  Returns its index (or -1)
- * and the fraction lam in (0, 1] along the chord. */
-static int chord_quads(const ho_quad *quads, int32_t nq, const double a[3], const double b[3], double *lam_hit)
+/* First surface crossed by the chord a -> b of one step: the side value
+ * changes sign, or is zero at b, after being non-zero at a.  Returns its id
+ * (or -1) and the fraction lam in (0, 1] along the chord. */
+static int chord_scene(const ho_scene *sc, const double a[3], const double b[3], double *lam_hit)
 {
     int best = -1;
     double bl = 2.0;
-    for (int32_t k = 0; k < nq; ++k) {
-        double sa = quad_side(&quads[k], a), sb = quad_side(&quads[k], b);
+    for (int32_t j = 0; j < sc->nq + sc->nt; ++j) {
+        double sa = surf_side(sc, j, a), sb = surf_side(sc, j, b);
         if (sa == 0.0 || (sa > 0.0 && sb > 0.0) || (sa < 0.0 && sb < 0.0)) continue;
         double lam = sa / (sa - sb);
         if (!(lam < bl)) continue;
         double h[3] = {a[0] + lam * (b[0] - a[0]), a[1] + lam * (b[1] - a[1]), a[2] + lam * (b[2] - a[2])};
-        if (!in_quad(&quads[k], h)) continue;
-        best = k;
+        if (!surf_inside(sc, j, h)) continue;
+        best = surf_id(sc, j);
         bl = lam;
     }
     *lam_hit = bl;
@@ -487,16 +549,16 @@ double ho_advance(const ho_medium *md, const ho_step *st, double te, double c[3]
  * box; inside, Eq. 16 is applied with the step of Eq. 18 (or the fixed step).
  * Returns the status; x_out / w_out get the last position and direction.
  *
- * With scene quads (nq > 0): a quad met by the straight ray before the box
- * ends the ray there (x_out = o, no steps); inside the box each step's chord
- * C_k -> C_{k+1} is tested and the first quad crossed ends the ray at the
- * crossing point (x_out = that point, w_out = omega_{k+1}).  *surf_out gets
- * the quad index and hit_out the point, or -1 when no quad was met on the way
- * (the caller then casts the straight exit ray). */
-static int march(const ho_medium *md, const ho_step *st, const ho_quad *quads, int32_t nq, const double o[3],
-                 const double d[3], double x_out[3], double w_out[3], int64_t *steps_out, double hit_out[3],
-                 int *surf_out)
+ * With scene surfaces (sc non-NULL): a surface met by the straight ray before
+ * the box ends the ray there (x_out = o, no steps); inside the box each step's
+ * chord C_k -> C_{k+1} is tested and the first surface crossed ends the ray at
+ * the crossing point (x_out = that point, w_out = omega_{k+1}).  *surf_out
+ * gets the surface id and hit_out the point, or -1 when none was met on the
+ * way (the caller then casts the straight exit ray). */
+static int march(const ho_medium *md, const ho_step *st, const ho_scene *sc, const double o[3], const double d[3],
+                 double x_out[3], double w_out[3], int64_t *steps_out, double hit_out[3], int *surf_out)
 {
+    const int nq = sc ? sc->nq + sc->nt : 0;
     const double *lo = md->grid.lo, *hi = md->grid.hi;
     double t_in, t_out;
     *steps_out = 0;
@@ -509,7 +571,7 @@ static int march(const ho_medium *md, const ho_step *st, const ho_quad *quads, i
     double s0 = t_in > 0.0 ? t_in : 0.0;
     if (nq > 0) {
         double th;
-        int qh = cast_quads(quads, nq, o, d, s0, &th);
+        int qh = cast_scene(sc, o, d, s0, &th);
         if (qh >= 0) {
             memcpy(x_out, o, sizeof(double) * 3);
             for (int a = 0; a < 3; ++a) hit_out[a] = o[a] + th * d[a];
@@ -533,7 +595,7 @@ static int march(const ho_medium *md, const ho_step *st, const ho_quad *quads, i
         }
         if (nq > 0) {
             double lam;
-            int qh = chord_quads(quads, nq, cp, c, &lam);
+            int qh = chord_scene(sc, cp, c, &lam);
             if (qh >= 0) {
                 for (int a = 0; a < 3; ++a) c[a] = cp[a] + lam * (c[a] - cp[a]);
                 memcpy(hit_out, c, sizeof(c));
@@ -705,10 +767,11 @@ static int decode_ray(const ho_view *views, int32_t nviews, int64_t id, int32_t 
  * before or inside the volume ends the ray (see march); otherwise the straight
  * exit ray is cast against the quads and the view's backdrop plane and the
  * nearest wins (quads win ties).  surface: 0 backdrop, k + 1 quad k, 255 none. */
-int ho_trace_scene(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_quad *quads, int32_t nq,
-                   const ho_step *st, const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos,
-                   double *exit_dir, int64_t *steps, uint8_t *status, uint8_t *surface)
+static int trace_impl(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_scene *sc,
+                      const ho_step *st, const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos,
+                      double *exit_dir, int64_t *steps, uint8_t *status, uint8_t *surface)
 {
+    const int nq = sc ? sc->nq + sc->nt : 0;
     cam_frame *cfs = (cam_frame *)malloc(sizeof(cam_frame) * (size_t)(nviews > 0 ? nviews : 1));
     if (!cfs) return -1;
     for (int32_t k = 0; k < nviews; ++k) camera_frame(&views[k], &cfs[k]);
@@ -725,12 +788,12 @@ int ho_trace_scene(const ho_medium *md, const ho_view *views, int32_t nviews, co
         int64_t k;
         int surf;
         pixel_ray(&cfs[vi], p, q, d);
-        int s = march(md, st, quads, nq, cfs[vi].eye, d, x, w, &k, hit, &surf);
+        int s = march(md, st, sc, cfs[vi].eye, d, x, w, &k, hit, &surf);
         int sid = 255;
         if (s != HO_NONFINITE) {
             if (surf < 0) {
                 double tq, tb = backdrop_t(&views[vi], x, w);
-                int qh = nq > 0 ? cast_quads(quads, nq, x, w, INFINITY, &tq) : -1;
+                int qh = nq > 0 ? cast_scene(sc, x, w, INFINITY, &tq) : -1;
                 if (qh >= 0 && (tb < 0.0 || tq <= tb)) {
                     surf = qh;
                     for (int a = 0; a < 3; ++a) hit[a] = x[a] + tq * w[a];
@@ -760,12 +823,31 @@ int ho_trace_scene(const ho_medium *md, const ho_view *views, int32_t nviews, co
     return bad ? -2 : 0;
 }
 
+int ho_trace_scene(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_quad *quads, int32_t nq,
+                   const ho_step *st, const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos,
+                   double *exit_dir, int64_t *steps, uint8_t *status, uint8_t *surface)
+{
+    ho_scene sc = {quads, nq, NULL, 0};
+    return trace_impl(md, views, nviews, nq > 0 ? &sc : NULL, st, ray_ids, nrays, disp, exit_pos, exit_dir, steps,
+                      status, surface);
+}
+
+/* ho_trace_scene with a triangle mesh instead of quads: surface ids are the
+ * triangles' `surf` values (a hit on triangle i reports tris[i].surf + 1). */
+int ho_trace_mesh(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_tri *tris, int32_t nt,
+                  const ho_step *st, const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos,
+                  double *exit_dir, int64_t *steps, uint8_t *status, uint8_t *surface)
+{
+    ho_scene sc = {NULL, 0, tris, nt};
+    return trace_impl(md, views, nviews, nt > 0 ? &sc : NULL, st, ray_ids, nrays, disp, exit_pos, exit_dir, steps,
+                      status, surface);
+}
+
 int ho_trace_views(const ho_medium *md, const ho_view *views, int32_t nviews, const ho_step *st,
                    const int64_t *ray_ids, int64_t nrays, double *disp, double *exit_pos, double *exit_dir,
                    int64_t *steps, uint8_t *status)
 {
-    return ho_trace_scene(md, views, nviews, NULL, 0, st, ray_ids, nrays, disp, exit_pos, exit_dir, steps, status,
-                          NULL);
+    return trace_impl(md, views, nviews, NULL, st, ray_ids, nrays, disp, exit_pos, exit_dir, steps, status, NULL);
 }
 
 /* March explicit rays (origin, unit direction) without a camera. */
@@ -778,7 +860,7 @@ int ho_trace_rays(const ho_medium *md, const ho_step *st, const double *origins,
         int64_t k;
         double hit[3];
         int surf;
-        int s = march(md, st, NULL, 0, origins + 3 * i, dirs + 3 * i, x, w, &k, hit, &surf);
+        int s = march(md, st, NULL, origins + 3 * i, dirs + 3 * i, x, w, &k, hit, &surf);
         for (int a = 0; a < 3; ++a) {
             exit_pos[3 * i + a] = x[a];
             exit_dir[3 * i + a] = w[a];
@@ -875,7 +957,7 @@ int ho_reference_views(const ho_medium *md, const ho_view *views, int32_t nviews
             st.max_steps = INT64_MAX;
             double hit[3];
             int surf;
-            march(md, &st, NULL, 0, cfs[vi].eye, d, cur_x, cur_w, &k, hit, &surf);
+            march(md, &st, NULL, cfs[vi].eye, d, cur_x, cur_w, &k, hit, &surf);
             cur_d[0] = cur_d[1] = NAN;
             backdrop_disp(&cfs[vi], &views[vi], p, q, cur_x, cur_w, cur_d);
             if (have_prev) {
