@@ -112,6 +112,15 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *   "splat.brick_z"        gather brick depth BZ: 4 or 8 voxels, 0 = the one
  *                          that brings the brick closer to twice as deep as
  *                          wide (default 0)
+ *   "splat.scan_fault_test" 1: the next splat calls' one-pass cell-list scans
+ *                          wait for tile sums that never come, with a short
+ *                          bound, so that the failure path runs (default 0;
+ *                          for tests).  A scan whose bounded wait gives up
+ *                          leaves NaN in the field it builds, the field is
+ *                          marked unusable, and the first library call that
+ *                          runs after the failing work has completed returns
+ *                          HZ_E_DEVICE (as does every later call given that
+ *                          field).
  * Errors: HZ_E_INVALID (unknown key or value out of range). */
 hz_status hz_ctx_tune(hz_ctx *ctx, const char *key, int64_t value);
 
@@ -129,28 +138,6 @@ hz_status hz_profile_enable(hz_ctx *ctx, int32_t enable);
  * alone.  Errors: HZ_E_INVALID (unknown group name). */
 hz_status hz_profile_select(hz_ctx *ctx, const char *groups);
 hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches, int32_t reset);
-
-/* Achievable read bandwidth (GB/s) of a device buffer of `bytes` read `reps`
- * times by a plain streaming kernel: buffers far above the 256 MB MALL measure
- * HBM, field-sized ones measure the caches that serve the tracer.  Allocates
- * (and frees) the buffer against the budget; synchronises `hip_stream`.
- * Errors: HZ_E_INVALID (bytes < 4096, reps outside [1, 10000]), HZ_E_BUDGET,
- * HZ_E_NOMEM, HZ_E_DEVICE. */
-hz_status hz_membench(hz_ctx *ctx, uint64_t bytes, int32_t reps, double *read_gbps, void *hip_stream);
-
-/* Achievable gather bandwidth (GB/s) of the tracer's access pattern with no
- * arithmetic around it: `walkers` straight rays (8 x 8 pixel tiles of one
- * image, entering the z = 0 face of a res[0] x res[1] x res[2] grid of
- * `voxel_bytes`-byte voxels, 16 as F32 fields and 8 as F16/BF16 ones) each
- * take `steps` steps of one voxel, reading the 8 corners of their cell per
- * step the way the marcher does; counted as walkers x steps x 8 x voxel_bytes
- * per launch, `reps` timed launches after one warm-up.  Allocates (and frees)
- * the grid against the budget; synchronises `hip_stream`.
- * Errors: HZ_E_INVALID (voxel_bytes not 8 or 16, res outside [2, 65535] or a
- * grid of 2^31 voxels or more, walkers outside [1, 2^26], steps outside
- * [1, 65536], reps outside [1, 10000]), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
-hz_status hz_membench_gather(hz_ctx *ctx, const int32_t res[3], int32_t voxel_bytes, int32_t walkers, int32_t steps,
-                             int32_t reps, double *gather_gbps, void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
 /* Index field (paper Sec. 3.3.1, Eqs. 12-13)                             */
@@ -325,6 +312,38 @@ hz_status hz_trace_scene(hz_ctx *ctx, const hz_field *field, const hz_view *view
                          const hz_trace_out *out, uint8_t *surface, void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* Measurement: achievable bandwidth of the memory levels the tracer uses   */
+/* ---------------------------------------------------------------------- */
+
+/* Achievable read bandwidth (GB/s) of a device buffer of `bytes` read `reps`
+ * times by a plain streaming kernel: buffers far above the 256 MB MALL measure
+ * HBM, field-sized ones measure the caches that serve the tracer.  Allocates
+ * (and frees) the buffer against the budget; synchronises `hip_stream`.
+ * Errors: HZ_E_INVALID (bytes < 4096, reps outside [1, 10000]), HZ_E_BUDGET,
+ * HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_membench(hz_ctx *ctx, uint64_t bytes, int32_t reps, double *read_gbps, void *hip_stream);
+
+/* Achievable gather bandwidth (GB/s) of the tracer's access pattern with no
+ * arithmetic around it, replaying the tracer's own rays: every pixel of
+ * views[0..nviews) casts the pinhole ray hz_trace_views casts (one thread per
+ * pixel, 8 x 8 pixel tiles per wave, view after view) and, if the ray enters
+ * the box of `grid`, walks straight through it in steps of step_len metres
+ * from the entry point, reading at every sample the 8 corner voxels of its
+ * cell the way the marcher does.  The grid holds voxel_bytes-byte voxels (16
+ * as F32 fields, 8 as F16/BF16 ones).  Counted as samples x 8 x voxel_bytes
+ * per launch (*samples, may be NULL, gets the samples per launch); one
+ * warm-up launch, then `reps` timed ones.  Allocates (and frees) the grid
+ * against the budget; synchronises hip_stream.
+ * Errors: HZ_E_INVALID (NULL grid/views/gather_gbps, voxel_bytes not 8 or 16,
+ * res outside [2, 65535] or a grid of 2^31 voxels or more, bad views, nviews
+ * outside [1, 4096], step_len outside [1e-3, 1e3] voxels, reps outside
+ * [1, 10000]; after the run: no ray enters the grid), HZ_E_BUDGET,
+ * HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_membench_gather(hz_ctx *ctx, const hz_grid *grid, int32_t voxel_bytes, const hz_view *views,
+                             int32_t nviews, float step_len, int32_t reps, double *gather_gbps, int64_t *samples,
+                             void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of multi-view requests                   */
 /* ---------------------------------------------------------------------- */
 
@@ -359,7 +378,16 @@ hz_status hz_poll(hz_ctx *ctx, hz_ticket ticket, double *latency_s);
  * of rays.  Errors: HZ_E_NOTFOUND, HZ_E_INVALID (not complete yet). */
 hz_status hz_request_outputs(hz_ctx *ctx, hz_ticket ticket, hz_trace_out *out, int64_t *nrays);
 
-/* Free a completed request's outputs and forget its ticket. */
+/* Device timestamps (milliseconds from the server's start, on the GPU's own
+ * clock) of the first and last kernel of the launch that carried a completed
+ * request; requests batched together share them, and launches on different
+ * slots may overlap.  Errors: HZ_E_NOTFOUND, HZ_E_INVALID (not complete). */
+hz_status hz_request_timing(hz_ctx *ctx, hz_ticket ticket, double *device_start_ms, double *device_end_ms);
+
+/* Release a completed (or still pending) request and forget its ticket.  Its
+ * output memory goes back to the server's pool and is reused by later
+ * requests, so every read of the outputs (including device work queued on
+ * other streams) must have completed first.  Never blocks on the device. */
 hz_status hz_request_release(hz_ctx *ctx, hz_ticket ticket);
 
 /* Stop the serving loop after the requests already admitted have finished;

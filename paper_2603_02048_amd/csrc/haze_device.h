@@ -40,6 +40,17 @@ struct CellGrid {
 // (4 or 8, whichever makes the brick closer to a cube).
 constexpr int SPLAT_BX = 8, SPLAT_BY = 8;
 
+// Bounded wait of the one-pass cell-list scan: spin_limit sleeps per lower
+// tile before the wait gives up (tag_bias != 0 only in the fault test, where no
+// tag matches); a wait that gives up stores `serial` into fail_host, a word
+// of host memory the library reads at its next call.
+struct ScanGuard {
+    uint32_t spin_limit;
+    uint32_t tag_bias;
+    uint32_t *fail_host;
+    uint32_t serial;
+};
+
 // Geometry and constants of one splat launch.
 struct SplatParams {
     float lo[3];          // grid box corner
@@ -81,7 +92,8 @@ struct alignas(16) TraceJob {
     float *exit_dir;
     uint32_t *steps;
     uint8_t *status;
-    uint8_t *surface;     // optional: 0 backdrop, k + 1 scene quad k, 255 none
+    uint8_t *surface;     // optional: 0 backdrop, k + 1 scene quad k (or mesh surface k), 255 none
+    uint32_t *tri_tests;  // optional (mesh scenes): exact ray-triangle tests the ray took
 };
 
 struct TraceGrid {
@@ -108,6 +120,7 @@ struct TraceOutFlat {      // outputs indexed by queue position (ray-subset mode
     uint32_t *steps;
     uint8_t *status;
     uint8_t *surface;
+    uint32_t *tri_tests;
 };
 
 // A planar scene board (parallelogram), as affine functions of the position:
@@ -121,6 +134,29 @@ struct SceneQuad {
     float n[3], n0;
     float du[3], du0;
     float dv[3], dv0;
+};
+
+// A triangle-mesh scene (paper Sec. 4.1): each triangle as a SceneQuad whose
+// u, v functions are the barycentric coordinates (inside: u, v >= 0,
+// u + v <= 1), and a conservative shell on a coarse grid: per cell a lower
+// bound of the distance from any point of the cell to the mesh, and the list
+// of triangles within `reach` (the longest chord served) of the cell.  A chord
+// of a march step starting in a cell whose bound exceeds the step length
+// cannot meet the mesh and takes no exact test; straight rays walk the cells
+// they cross (3D DDA) and test the cells' lists.  brute = 1: no shell, every
+// test against every triangle (for comparison).
+struct MeshLaunch {
+    const SceneQuad *tris;
+    const uint8_t *surf;       // surface id of each triangle (a hit reports it + 1)
+    const float *dlow;         // per cell
+    const uint32_t *start;     // per cell, ncells + 1 entries
+    const uint32_t *list;      // triangle indices, ascending within a cell
+    float lo[3];               // shell grid corner
+    float cell;                // cell edge
+    float inv_cell;
+    int32_t res[3];
+    int32_t ntris;
+    int32_t brute;
 };
 
 struct TraceLaunch {
@@ -142,6 +178,7 @@ struct TraceLaunch {
     int32_t ninner;        // boards that may cross the volume: tested on every step
     uint32_t inner_idx;    // their indices, one byte each (lowest byte first)
     const SceneQuad *quads;  // device copy of the nquads boards
+    MeshLaunch mesh;       // triangle-mesh scene (mesh.ntris > 0), exclusive of boards
 };
 
 // Ray generation sorts the entering rays by their straight chord through the

@@ -1,15 +1,23 @@
 // membench.hip -- achievable read bandwidth of the memory level a buffer of a
 // given size lives in (HBM for buffers far above the 256 MB MALL, L2/MALL for
 // field-sized buffers read repeatedly), and of the tracer's own access pattern
-// (coherent 8-corner gathers along straight rays through a field-sized grid)
-// with no arithmetic around it.  Used to put the tracer's gather rate next to
-// what the memory system actually delivers.
+// (8-corner gathers along the benchmarked views' own pinhole rays, walked
+// straight through a field-sized grid) with no arithmetic around it.  Used to
+// put the tracer's gather rate next to what the memory system delivers.
 #include "haze.h"
+#include "ray_geom.h"
 #include "serve.h"
+#include "serve_policy.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 namespace haze {
+hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
+                   const char *fn, int index);
+void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G);
 
 // Grid-stride read of n float4; each block writes one partial sum so the
 // loads cannot be optimised away.
@@ -40,53 +48,75 @@ __global__ void k_init(float4 *a, int64_t n)
 typedef uint32_t gb_u32x4 __attribute__((ext_vector_type(4), aligned(8)));
 typedef const gb_u32x4 __attribute__((address_space(1))) *gb_ptr;
 
-// One 8 x 8 pixel tile per wave, like the tracer's ray generation: walker
-// (tile, lane) starts on the z = 0 face of an rx x ry x rz grid of EB-byte
-// voxels at its pixel and walks a straight line one voxel per step, its
-// direction tilted with its pixel's offset from the image centre (up to 1/4
-// voxel per step sideways, a 28 degree field of view).  Each step reads the 8
-// corners of its cell as the tracer does (the two x-neighbours of each of the
-// 4 rows in one 16 or 32 byte stretch); indices are clamped into the grid.
-// The words are folded into one value per walker so no load can be dropped.
+// One thread per queue slot of the views, in the tracer's order (8 x 8 pixel
+// tiles, view after view): the thread casts its pixel's pinhole ray and, if
+// it enters the grid box, walks straight through it in steps of `step`
+// metres from the entry point, reading at every sample the 8 corners of its
+// cell as the marcher does (cell index clamped to [0, R-2]; the two
+// x-neighbours of each of the 4 rows in one 16 or 32 byte stretch).  The words
+// are folded into one value per thread so no load can be dropped; the samples
+// are counted (one atomic per wave).
 template <int EB>
-__global__ __launch_bounds__(256) void k_gather(const char *__restrict__ f, int32_t rx, int32_t ry, int32_t rz,
-                                                int32_t walkers, int32_t tiles_x, int32_t steps,
-                                                uint32_t *__restrict__ sink)
+__global__ __launch_bounds__(256) void k_gather_views(const char *__restrict__ f, TraceGrid G,
+                                                      const TraceJob *__restrict__ jobs, int32_t njobs,
+                                                      int64_t nslots, float step, uint32_t *__restrict__ sink,
+                                                      unsigned long long *__restrict__ nsamples)
 {
-    const int32_t w = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (w >= walkers) return;
-    const int32_t tile = w >> 6, lane = w & 63;
-    const int32_t tiles_y = (walkers + 64 * tiles_x - 1) / (64 * tiles_x);
-    const float iw = 1.0f / (float)(8 * tiles_x), ih = 1.0f / (float)(8 * tiles_y);
-    const float u = ((float)((tile % tiles_x) * 8 + (lane & 7)) + 0.5f) * iw;   // (0, 1)
-    const float v = ((float)((tile / tiles_x) * 8 + (lane >> 3)) + 0.5f) * ih;
-    float x = u * (float)(rx - 1), y = v * (float)(ry - 1), z = 0.0f;
-    const float dx = 0.5f * (u - 0.5f), dy = 0.5f * (v - 0.5f);
-    const float inv = __builtin_amdgcn_rsqf(1.0f + dx * dx + dy * dy);
-    const float sx = dx * inv, sy = dy * inv, sz = inv;
-    const uint32_t row = (uint32_t)rx, slab = (uint32_t)rx * (uint32_t)ry;
-    uint32_t acc = 0u;
-    for (int32_t k = 0; k < steps; ++k) {
-        const uint32_t ix = (uint32_t)__builtin_amdgcn_fmed3f(floorf(x), 0.0f, (float)(rx - 2));
-        const uint32_t iy = (uint32_t)__builtin_amdgcn_fmed3f(floorf(y), 0.0f, (float)(ry - 2));
-        const uint32_t iz = (uint32_t)__builtin_amdgcn_fmed3f(floorf(z), 0.0f, (float)(rz - 2));
-        const uint32_t b = iz * slab + iy * row + ix;
-        const uint32_t c[4] = {b, b + row, b + slab, b + slab + row};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const gb_ptr p = (gb_ptr)(f + (size_t)c[j] * EB);
-            const gb_u32x4 a = p[0];
-            acc ^= (a.x ^ a.y) ^ (a.z ^ a.w);
-            if (EB == 16) {
-                const gb_u32x4 b2 = p[1];
-                acc ^= (b2.x ^ b2.y) ^ (b2.z ^ b2.w);
-            }
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0u, n = 0u;
+    if (slot < nslots) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].slot_begin <= slot)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
-        x += sx;
-        y += sy;
-        z += sz;
+        const TraceJob &J = jobs[lo];
+        const int32_t local = (int32_t)(slot - J.slot_begin);
+        const int32_t tile = local >> 6, within = local & 63;
+        const int32_t ty = tile / J.tiles_x;
+        const int32_t p = (tile - ty * J.tiles_x) * 8 + (within & 7), q = ty * 8 + (within >> 3);
+        float t0 = 0.0f, t1 = 0.0f;
+        float d[3] = {0.0f, 0.0f, 0.0f};
+        bool in = false;
+        if (p < J.width && q < J.height) {
+            const float3 d3 = pixel_dir(J, p, q);
+            d[0] = d3.x;
+            d[1] = d3.y;
+            d[2] = d3.z;
+            in = enter_volume(G, J.eye, d, t0, &t1);
+        }
+        const uint32_t row = (uint32_t)G.res[0], slab = (uint32_t)G.res[0] * (uint32_t)G.res[1];
+        for (uint32_t k = 0; in; ++k) {
+            const float t = fmaf((float)k, step, t0);
+            if (!(t < t1)) break;
+            uint32_t i[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float u = fmaf(fmaf(t, d[a], J.eye[a]), G.inv_sp[a], G.off[a]);
+                i[a] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, G.maxi[a]);
+            }
+            const uint32_t b = (i[2] * slab + i[1] * row) + i[0];
+            const uint32_t c[4] = {b, b + row, b + slab, b + slab + row};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const gb_ptr pp = (gb_ptr)(f + (size_t)c[j] * EB);
+                const gb_u32x4 a = pp[0];
+                acc ^= (a.x ^ a.y) ^ (a.z ^ a.w);
+                if (EB == 16) {
+                    const gb_u32x4 b2 = pp[1];
+                    acc ^= (b2.x ^ b2.y) ^ (b2.z ^ b2.w);
+                }
+            }
+            ++n;
+        }
+        sink[slot] = acc;
     }
-    sink[w] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += (uint32_t)__shfl_xor((int)n, off);
+    if ((threadIdx.x & 63) == 0 && n) atomicAdd(nsamples, (unsigned long long)n);
 }
 
 }  // namespace haze
@@ -130,56 +160,84 @@ extern "C" hz_status hz_membench(hz_ctx *c, uint64_t bytes, int32_t reps, double
     return HZ_OK;
 }
 
-extern "C" hz_status hz_membench_gather(hz_ctx *c, const int32_t res[3], int32_t voxel_bytes, int32_t walkers,
-                                        int32_t steps, int32_t reps, double *gather_gbps, void *hip_stream)
+extern "C" hz_status hz_membench_gather(hz_ctx *c, const hz_grid *grid, int32_t voxel_bytes, const hz_view *views,
+                                        int32_t nviews, float step_len, int32_t reps, double *gather_gbps,
+                                        int64_t *samples, void *hip_stream)
 {
-    if (!c || !res || !gather_gbps) return set_error(HZ_E_INVALID, "hz_membench_gather: NULL argument");
-    if (voxel_bytes != 8 && voxel_bytes != 16) return set_error(HZ_E_INVALID, "hz_membench_gather: voxel_bytes not 8 or 16");
-    for (int a = 0; a < 3; ++a)
-        if (res[a] < 2 || res[a] > 65535) return set_error(HZ_E_INVALID, "hz_membench_gather: res outside [2, 65535]");
-    const int64_t nvox = (int64_t)res[0] * res[1] * res[2];
+    const char *fn = "hz_membench_gather";
+    if (!c || !grid || !views || !gather_gbps) return set_error(HZ_E_INVALID, "hz_membench_gather: NULL argument");
+    if (voxel_bytes != 8 && voxel_bytes != 16)
+        return set_error(HZ_E_INVALID, "hz_membench_gather: voxel_bytes not 8 or 16");
+    int64_t nvox = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->res[a] < 2 || grid->res[a] > 65535 || !(grid->hi[a] > grid->lo[a]))
+            return set_error(HZ_E_INVALID, "hz_membench_gather: grid res outside [2, 65535] or hi <= lo");
+        nvox *= grid->res[a];
+    }
     if (nvox >= (1ll << 31)) return set_error(HZ_E_INVALID, "hz_membench_gather: grid of 2^31 voxels or more");
-    if (walkers < 1 || walkers > (1 << 26) || steps < 1 || steps > 65536 || reps < 1 || reps > 10000)
-        return set_error(HZ_E_INVALID, "hz_membench_gather: walkers, steps or reps out of range");
+    if (nviews < 1 || nviews > 4096 || reps < 1 || reps > 10000)
+        return set_error(HZ_E_INVALID, "hz_membench_gather: nviews or reps out of range");
+    double vox = 1e300;
+    for (int a = 0; a < 3; ++a) vox = std::min(vox, (grid->hi[a] - grid->lo[a]) / grid->res[a]);
+    if (!(step_len >= 1e-3 * vox && step_len <= 1e3 * vox))
+        return set_error(HZ_E_INVALID, "hz_membench_gather: step_len outside [1e-3, 1e3] voxels");
+    std::vector<TraceJob> jobs((size_t)nviews);
+    int64_t nslots = 0;
+    for (int i = 0; i < nviews; ++i) {
+        hz_status st = make_job(&views[i], nullptr, nslots, 0, &jobs[(size_t)i], fn, i);
+        if (st != HZ_OK) return st;
+        nslots += view_slots(views[i].width, views[i].height);
+    }
+    if (nslots > INT32_MAX) return set_error(HZ_E_INVALID, "hz_membench_gather: more than 2^31 - 1 rays");
+    TraceGrid G;
+    make_trace_grid(*grid, 1.0f, &G);
     if (hipSetDevice(ctx_device(c)) != hipSuccess) return set_error(HZ_E_DEVICE, "hz_membench_gather: hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    // a pixel image about as wide as the grid is high in voxels, 8 x 8 tiles
-    const int32_t tiles = (walkers + 63) / 64;
-    int32_t tiles_x = 1;
-    while ((int64_t)tiles_x * tiles_x * 9 < (int64_t)tiles * 16) ++tiles_x;   // ~16:9 image
     const size_t fbytes = (size_t)nvox * (size_t)voxel_bytes;
-    void *buf = nullptr, *sink = nullptr;
+    const size_t jbytes = sizeof(TraceJob) * jobs.size();
+    const size_t sbytes = 4u * (size_t)nslots + 256;
+    void *buf = nullptr, *aux = nullptr;
     hz_status st = ctx_alloc(c, &buf, fbytes);
     if (st != HZ_OK) return st;
-    st = ctx_alloc(c, &sink, sizeof(uint32_t) * (size_t)walkers);
+    st = ctx_alloc(c, &aux, 256 + jbytes + sbytes);
     if (st != HZ_OK) {
         ctx_free(c, buf, fbytes);
         return st;
     }
+    unsigned long long *count = (unsigned long long *)aux;
+    TraceJob *djobs = (TraceJob *)((char *)aux + 256);
+    uint32_t *sink = (uint32_t *)((char *)aux + 256 + jbytes);
     const int64_t n4 = (int64_t)(fbytes / 16);
-    const dim3 g((unsigned)((walkers + 255) / 256)), b(256);
+    const dim3 g((unsigned)((nslots + 255) / 256)), b(256);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms = 0.0f;
-    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    unsigned long long total = 0;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMemcpyAsync(djobs, jobs.data(), jbytes, hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemsetAsync(count, 0, 8, s) == hipSuccess;
     if (ok) {
         hipLaunchKernelGGL(k_init, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, (float4 *)buf, n4);
-        for (int r = 0; r <= reps; ++r) {   // launch 0 warms the caches
+        for (int r = 0; r <= reps; ++r) {   // launch 0 warms the caches and counts the samples
             if (r == 1) ok = hipEventRecord(e0, s) == hipSuccess;
+            unsigned long long *cnt = r == 0 ? count : count + 1;
             if (voxel_bytes == 16)
-                hipLaunchKernelGGL(k_gather<16>, g, b, 0, s, (const char *)buf, res[0], res[1], res[2], walkers,
-                                   tiles_x, steps, (uint32_t *)sink);
+                hipLaunchKernelGGL(k_gather_views<16>, g, b, 0, s, (const char *)buf, G, (const TraceJob *)djobs,
+                                   nviews, nslots, step_len, sink, cnt);
             else
-                hipLaunchKernelGGL(k_gather<8>, g, b, 0, s, (const char *)buf, res[0], res[1], res[2], walkers,
-                                   tiles_x, steps, (uint32_t *)sink);
+                hipLaunchKernelGGL(k_gather_views<8>, g, b, 0, s, (const char *)buf, G, (const TraceJob *)djobs,
+                                   nviews, nslots, step_len, sink, cnt);
         }
         ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-             hipEventElapsedTime(&ms, e0, e1) == hipSuccess && hipGetLastError() == hipSuccess;
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess && hipGetLastError() == hipSuccess &&
+             hipMemcpy(&total, count, 8, hipMemcpyDeviceToHost) == hipSuccess;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     ctx_free(c, buf, fbytes);
-    ctx_free(c, sink, sizeof(uint32_t) * (size_t)walkers);
+    ctx_free(c, aux, 256 + jbytes + sbytes);
     if (!ok || ms <= 0.0f) return set_error(HZ_E_DEVICE, "hz_membench_gather: timing failed");
-    *gather_gbps = (double)walkers * steps * 8.0 * voxel_bytes * reps / (ms * 1e-3) / 1e9;
+    if (total == 0) return set_error(HZ_E_INVALID, "hz_membench_gather: no ray of the views enters the grid");
+    if (samples) *samples = (int64_t)total;
+    *gather_gbps = (double)total * 8.0 * voxel_bytes * reps / (ms * 1e-3) / 1e9;
     return HZ_OK;
 }

@@ -24,13 +24,15 @@
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
                             uint32_t *, uint32_t *, int64_t, uint32_t *, uint32_t *, uint32_t *, float4 *, void *,
-                            bool, uint32_t *, bool, hipStream_t, const KTimer &);
+                            bool, uint32_t *, bool, const ScanGuard &, hipStream_t, const KTimer &);
 int32_t scan_tiles(int32_t ncells);
 size_t scan_scratch_bytes(int32_t ncells);
 bool scan_is_onepass(int32_t ncells);
-hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, hipStream_t, const KTimer &);
+uint32_t *scan_fail_word(void *scan);
+hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, const uint32_t *, hipStream_t,
+                        const KTimer &);
 hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const float4 *, const uint32_t *, float *,
-                                hipStream_t, const KTimer &);
+                                const uint32_t *, hipStream_t, const KTimer &);
 int scatter_max_rows(const SplatParams &P);
 int scatter_rows_limit();
 hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t,
@@ -104,6 +106,8 @@ struct hz_field {
     CallMark made;                 // the call that wrote the field
     std::vector<CallMark> uses;    // the latest call on each stream that touched it
     std::mutex mu;
+    uint32_t serial = 0;           // splat call that built it (0: built from a grid)
+    bool bad = false;              // that call's cell-list scan failed: the field holds NaN
 };
 
 struct hz_ctx {
@@ -132,6 +136,12 @@ struct hz_ctx {
     int32_t blocks_per_cu = 0;   // 0: as many as fit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8
+    int32_t scan_fault_test = 0; // 1: the one-pass scan's waits give up (fault test)
+    // host-visible word (pinned, device-mapped) where a failed scan leaves
+    // the serial number of its splat call; splat calls are numbered from 1
+    uint32_t *fault_word = nullptr;
+    uint32_t *fault_word_dev = nullptr;
+    uint32_t splat_serial = 0;
     std::vector<hz_field *> fields;
     std::mutex fields_mu;
     // memory of released fields, reused in stream order (no host sync)
@@ -194,6 +204,22 @@ hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes)
     return HZ_OK;
 }
 
+// ctx_alloc without giving back pooled field memory: never waits for the
+// device or frees anything (HZ_E_BUDGET when the budget has no room).
+hz_status ctx_alloc_nowait(hz_ctx *c, void **p, size_t bytes)
+{
+    if (!ledger_take(c, bytes))
+        return fail(HZ_E_BUDGET, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu bytes in use)",
+                    bytes, (unsigned long long)c->used.load(), (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(p, bytes == 0 ? 256 : bytes);
+    if (e != hipSuccess) {
+        ledger_give(c, bytes);
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    return HZ_OK;
+}
+
 void ctx_free(hz_ctx *c, void *p, size_t bytes)
 {
     if (p) (void)hipFree(p);
@@ -201,6 +227,10 @@ void ctx_free(hz_ctx *c, void *p, size_t bytes)
 }
 
 int ctx_device(const hz_ctx *c) { return c->device; }
+
+// Give back pooled (released) field memory until `bytes` more fit the budget;
+// waits for the blocks' last uses.
+void ctx_trim_pool(hz_ctx *c, size_t bytes) { pool_trim(c, bytes); }
 
 // Budget left, counting pooled (released) field memory as available.
 uint64_t ctx_mem_avail(const hz_ctx *c)
@@ -332,7 +362,46 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
         c->march_bpc_scene[1][d] = march_blocks_per_cu(d, 2);
     }
     c->pinned.resize(8);
+    void *fw = nullptr, *fwd = nullptr;
+    if (hipHostMalloc(&fw, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&fwd, fw, 0) != hipSuccess) {
+        if (fw) (void)hipHostFree(fw);
+        delete c;
+        return fail(HZ_E_NOMEM, "hz_ctx_create: pinned host word for device fault reports");
+    }
+    c->fault_word = (uint32_t *)fw;
+    c->fault_word_dev = (uint32_t *)fwd;
+    *c->fault_word = 0u;
     *out = c;
+    return HZ_OK;
+}
+
+// A failed cell-list scan (k_scan_onepass gave up a bounded wait) leaves the
+// serial number of its splat call in the context's host-visible word: the
+// field that call built is marked bad and the calling entry point reports
+// HZ_E_DEVICE (once per failure).
+static hz_status take_device_fault(hz_ctx *c, const char *fn)
+{
+    const uint32_t serial = __atomic_exchange_n(c->fault_word, 0u, __ATOMIC_ACQ_REL);
+    if (!serial) return HZ_OK;
+    {
+        std::lock_guard<std::mutex> g(c->fields_mu);
+        for (hz_field *f : c->fields)
+            if (f->serial == serial) f->bad = true;
+    }
+    return fail(HZ_E_DEVICE,
+                "%s: the cell-list scan of an earlier hz_splat_index_field call (serial %u) gave up waiting for a "
+                "tile sum; the field it built holds NaN and is unusable", fn, serial);
+}
+
+// Entry check of a call that reads a field: pending fault reports first, then
+// the field's own state.
+static hz_status check_field_usable(hz_ctx *c, const hz_field *f, const char *fn)
+{
+    hz_status st = take_device_fault(c, fn);
+    if (st != HZ_OK) return st;
+    if (f->bad)
+        return fail(HZ_E_DEVICE, "%s: the field was built by a splat call whose cell-list scan failed", fn);
     return HZ_OK;
 }
 
@@ -513,6 +582,7 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
     }
     for (hipEvent_t e : c->marks)
         if (e) (void)hipEventDestroy(e);
+    if (c->fault_word) (void)hipHostFree(c->fault_word);
     delete c;
 }
 
@@ -533,6 +603,9 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
     } else if (k == "splat.method") {
         if (value < 0 || value > 2) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.method must be 0, 1 or 2");
         c->splat_method = (int32_t)value;
+    } else if (k == "splat.scan_fault_test") {
+        if (value != 0 && value != 1) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.scan_fault_test must be 0 or 1");
+        c->scan_fault_test = (int32_t)value;
     } else {
         return fail(HZ_E_INVALID, "hz_ctx_tune: unknown key '%s'", key);
     }
@@ -699,6 +772,8 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     if (!std::isfinite(prm->k_gd)) return fail(HZ_E_INVALID, "%s: k_gd must be finite", fn);
     st = check_dtype(prm->dtype, prm->store_scale, fn);
     if (st != HZ_OK) return st;
+    st = take_device_fault(c, fn);
+    if (st != HZ_OK) return st;
 
     // cell list over the grid box grown by the support 2h, cells of edge h
     CellGrid cg{};
@@ -768,14 +843,24 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     // three-pass scan, or before its tickets would wrap.
     const int32_t ntiles = scan_tiles((int32_t)ncells);
     const int64_t clear_words = (c->count.clean && !scatter) ? 0 : (int64_t)(c->count.cap / 4);
-    const bool scan_reset = !c->tiles.clean || c->scan_base > 0xffffffffu - (uint32_t)ntiles - 1u;
+    // (the fault test also resets the scan, so that no stale tag can match the
+    // biased ones it waits for)
+    const bool scan_reset = !c->tiles.clean || c->scan_base > 0xffffffffu - (uint32_t)ntiles - 1u ||
+                            c->scan_fault_test;
     c->count.clean = false;
     c->tiles.clean = false;
+    if (++c->splat_serial == 0) c->splat_serial = 1;
+    f->serial = c->splat_serial;
+    ScanGuard guard{1u << 26, 0u, c->fault_word_dev, f->serial};
+    if (c->scan_fault_test) {
+        guard.spin_limit = 64;
+        guard.tag_bias = 1u << 30;
+    }
     const KTimer t0 = prof_timer(c, "cell_list");
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     clear_words, (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr,
                                     (uint32_t *)c->slots.ptr, (float4 *)c->sorted.ptr, c->tiles.ptr, scan_reset,
-                                    &c->scan_base, scatter, s, t0);
+                                    &c->scan_base, scatter, guard, s, t0);
     prof_commit(c, "cell_list", t0);
     if (e == hipSuccess) {
         c->count.clean = !scatter;
@@ -783,12 +868,14 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     }
     if (e == hipSuccess) {
         const KTimer t1 = prof_timer(c, "splat");
+        const uint32_t *fail_word = scan_fail_word(c->tiles.ptr);
         if (scatter)
             e = launch_splat_scatter(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr,
-                                     (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, s, t1);
+                                     (const uint32_t *)c->count.ptr + ncells + 1, (float *)c->dn.ptr, fail_word, s,
+                                     t1);
         else
             e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr,
-                             s, t1);
+                             fail_word, s, t1);
         prof_commit(c, "splat", t1);
     }
     if (e != hipSuccess) {
@@ -822,6 +909,8 @@ extern "C" hz_status hz_index_field_from_grid(hz_ctx *c, const float *dn, const 
     if (st != HZ_OK) return st;
     st = check_dtype(dtype, store_scale, fn);
     if (st != HZ_OK) return st;
+    st = take_device_fault(c, fn);
+    if (st != HZ_OK) return st;
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
     hz_field *f = nullptr;
@@ -846,10 +935,12 @@ extern "C" hz_status hz_field_read(hz_ctx *c, const hz_field *fc, float *dn, flo
     if (!c || !fc) return fail(HZ_E_INVALID, "hz_field_read: NULL argument");
     hz_field *f = const_cast<hz_field *>(fc);
     if (f->ctx != c) return fail(HZ_E_INVALID, "hz_field_read: field belongs to another context");
+    hz_status st = check_field_usable(c, f, "hz_field_read");
+    if (st != HZ_OK) return st;
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t nv = (int64_t)f->grid.res[0] * f->grid.res[1] * f->grid.res[2];
-    hz_status st = field_order_read(c, f, s);
+    st = field_order_read(c, f, s);
     if (st != HZ_OK) return st;
     HZ_HIP(launch_field_unpack((int)f->dtype, f->data, nv, 1.0f / f->store_scale, dn, gx, gy, gz, s), "unpack launch");
     CallMark done;
@@ -1093,20 +1184,28 @@ static hz_status make_scene(const hz_scene *scene, const hz_grid &g, TraceLaunch
     return HZ_OK;
 }
 
-static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
-                            const hz_scene *scene, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
-                            const hz_trace_out *out, uint8_t *surface, void *hip_stream, const char *fn)
+// Validation and launch description shared by the tracing entry points:
+// jobs[0..nviews) get the camera frames (queue order: 8x8 pixel tiles, view
+// after view) and, when all rays are traced, the per-view output pointers;
+// L gets everything but the scratch pointers.
+static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews, int32_t max_views,
+                               const hz_step *step, const int64_t *ray_ids, int64_t nrays, const hz_trace_out *out,
+                               uint8_t *surface, TraceJob *jobs, TraceLaunch *Lp, const char *fn)
 {
     if (!c || !fc || !views || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
-    hz_field *f = const_cast<hz_field *>(fc);
+    const hz_field *f = fc;
     if (f->ctx != c) return fail(HZ_E_INVALID, "%s: field belongs to another context", fn);
-    if (nviews < 1 || nviews > 4096) return fail(HZ_E_INVALID, "%s: nviews = %d outside [1, 4096]", fn, nviews);
+    if (nviews < 1) return fail(HZ_E_INVALID, "%s: nviews = %d < 1", fn, nviews);
+    if (nviews > max_views)
+        return fail(max_views < 4096 ? HZ_E_UNSUPPORTED : HZ_E_INVALID, "%s: nviews = %d above the limit of %d", fn,
+                    nviews, max_views);
     hz_status st = check_step(step, fn);
     if (st != HZ_OK) return st;
-    std::vector<TraceJob> jobs((size_t)nviews);
+    st = check_field_usable(c, f, fn);
+    if (st != HZ_OK) return st;
     int64_t slot = 0, ray = 0;
     for (int i = 0; i < nviews; ++i) {
-        st = make_job(&views[i], f->data, slot, ray, &jobs[(size_t)i], fn, i);
+        st = make_job(&views[i], f->data, slot, ray, &jobs[i], fn, i);
         if (st != HZ_OK) return st;
         const int64_t tiles = (int64_t)((views[i].width + 7) / 8) * ((views[i].height + 7) / 8);
         slot += tiles * 64;
@@ -1119,14 +1218,16 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     if (subset && (nrays < 0 || nrays > INT32_MAX)) return fail(HZ_E_INVALID, "%s: bad nrays %lld", fn,
                                                                (long long)nrays);
 
-    TraceLaunch L{};
+    TraceLaunch &L = *Lp;
+    L = TraceLaunch{};
     L.njobs = nviews;
     L.subset = subset ? 1 : 0;
     L.nslots = subset ? nrays : slot;
     L.ray_ids = ray_ids;
     L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status, surface};
     if (!subset)
-        for (TraceJob &J : jobs) {
+        for (int i = 0; i < nviews; ++i) {
+            TraceJob &J = jobs[i];
             const int64_t base = J.ray_begin;
             J.disp = out->disp ? out->disp + 2 * base : nullptr;
             J.exit_pos = out->exit_pos ? out->exit_pos + 3 * base : nullptr;
@@ -1135,12 +1236,35 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
             J.status = out->status ? out->status + base : nullptr;
             J.surface = surface ? surface + base : nullptr;
         }
-    std::vector<SceneQuad> quads;
-    st = make_scene(scene, f->grid, &L, quads, fn);
-    if (st != HZ_OK) return st;
     make_trace_grid(f->grid, f->store_scale, &L.grid);
     make_trace_step(*step, f->grid, &L.step);
     L.refill_min = c->refill_min;
+    L.inv_len_bin = length_bin_scale(f->grid);
+    return HZ_OK;
+}
+
+// Persistent march grid: what fits on the chip at once.
+static int march_grid_blocks(const hz_ctx *c, const TraceLaunch &L, int dt)
+{
+    const int64_t want_blocks = (L.nslots + 255) / 256;
+    const int fit = L.ninner > 0 ? c->march_bpc_scene[1][dt] : L.nquads > 0 ? c->march_bpc_scene[0][dt]
+                                                                            : c->march_bpc[dt];
+    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, fit) : fit;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus));
+}
+
+static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                            const hz_scene *scene, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                            const hz_trace_out *out, uint8_t *surface, void *hip_stream, const char *fn)
+{
+    std::vector<TraceJob> jobs((size_t)std::max(0, std::min(nviews, 4096)));
+    TraceLaunch L;
+    hz_status st = prepare_trace(c, fc, views, nviews, 4096, step, ray_ids, nrays, out, surface, jobs.data(), &L, fn);
+    if (st != HZ_OK) return st;
+    hz_field *f = const_cast<hz_field *>(fc);
+    std::vector<SceneQuad> quads;
+    st = make_scene(scene, f->grid, &L, quads, fn);
+    if (st != HZ_OK) return st;
     if (L.nslots == 0) return HZ_OK;
 
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -1166,16 +1290,8 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     L.counters = (uint32_t *)c->counters.ptr + (size_t)c->counter_set * kCounterSetWords;
     L.counters_next = (uint32_t *)c->counters.ptr + (size_t)(1 - c->counter_set) * kCounterSetWords;
     L.slot_bin = (uint8_t *)c->bins.ptr;
-    L.inv_len_bin = length_bin_scale(f->grid);
     const int dt = (int)f->dtype;
-    // persistent grid: what fits on the chip at once
-    const int64_t want_blocks = (L.nslots + 255) / 256;
-    const int fit = L.ninner > 0 ? c->march_bpc_scene[1][dt] : L.nquads > 0 ? c->march_bpc_scene[0][dt]
-                                                                            : c->march_bpc[dt];
-    const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, fit) : fit;
-    int64_t blocks64 = std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus);
-    blocks64 = std::max<int64_t>(1, blocks64);
-    const int blocks = (int)blocks64;
+    const int blocks = march_grid_blocks(c, L, dt);
     // this launch's counter set was cleared by the previous launch's ray
     // generation; new memory, or a set after a failed call, needs clearing
     const bool clear = !c->counters.clean;
@@ -1227,7 +1343,18 @@ hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out) { return mark_issue(
 void field_use(hz_field *f, const CallMark &t) { field_mark_used(f, t); }
 hz_status field_ready(hz_field *f, hipStream_t s) { return field_order_read(f->ctx, f, s); }
 int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
-KTimer profile_timer(hz_ctx *c, const char *name) { return prof_timer(c, name); }
-void profile_commit(hz_ctx *c, const char *name, const KTimer &t) { prof_commit(c, name, t); }
+// A time measured by the caller's own events, added to a group's sums when
+// profiling is on and the group selected.
+void profile_add(hz_ctx *c, const char *name, double ms)
+{
+    std::lock_guard<std::mutex> g(c->prof_mu);
+    if (!c->prof_on) return;
+    if (!c->prof_only.empty() && std::find(c->prof_only.begin(), c->prof_only.end(), name) == c->prof_only.end())
+        return;
+    auto &acc = c->prof_acc[name];
+    acc.first += ms;
+    acc.second += 1;
+}
 hz_status set_error(hz_status s, const char *msg) { return fail(s, "%s", msg); }
+hz_status field_usable(hz_ctx *c, const hz_field *f, const char *fn) { return check_field_usable(c, f, fn); }
 }  // namespace haze

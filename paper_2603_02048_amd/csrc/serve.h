@@ -12,7 +12,9 @@ void server_destroy(Server *s);
 
 // context/field accessors implemented in runtime.hip
 hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes);
+hz_status ctx_alloc_nowait(hz_ctx *c, void **p, size_t bytes);   // no pool trimming, no device waits
 void ctx_free(hz_ctx *c, void *p, size_t bytes);
+void ctx_trim_pool(hz_ctx *c, size_t bytes);   // waits for the device: never under the server lock
 int ctx_device(const hz_ctx *c);
 int ctx_num_cus(const hz_ctx *c);
 uint64_t ctx_mem_avail(const hz_ctx *c);
@@ -26,7 +28,7 @@ hz_status field_ready(hz_field *f, hipStream_t s);       // order a read on s af
 void field_use(hz_field *f, const CallMark &t);            // a read by the call with mark t
 hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out);
 int march_blocks(hz_ctx *c, int dt);
-KTimer profile_timer(hz_ctx *c, const char *name);
-void profile_commit(hz_ctx *c, const char *name, const KTimer &t);
+void profile_add(hz_ctx *c, const char *name, double ms);
 hz_status set_error(hz_status s, const char *msg);
+hz_status field_usable(hz_ctx *c, const hz_field *f, const char *fn);   // pending device faults, bad fields
 }  // namespace haze

@@ -12,6 +12,12 @@
 // admitted as soon as a slot and memory free up, and launches on different
 // slots overlap on the device.  A request's rays are computed exactly as in a
 // solo hz_trace_views call, whatever else shares the launch.
+//
+// Nothing on the serving path frees device memory or waits for the device
+// while holding the server lock: request outputs come from a pool of
+// size-classed blocks that released requests return to (a released request's
+// batch has completed), and blocks that must go (budget pressure, a slot's
+// grown view table) are freed by the scheduler with the lock dropped.
 #include "haze_device.h"
 #include "serve.h"
 #include "serve_policy.h"
@@ -46,15 +52,25 @@ struct Request {
     BatchKey key = zero_key();
     int64_t nrays = 0, nslots = 0, out_bytes = 0;
     void *out_mem = nullptr;
+    size_t out_cap = 0;         // size class of out_mem
     hz_trace_out out{};
     double t_submit = 0.0, t_done = 0.0;
+    double dev_start_ms = 0.0, dev_end_ms = 0.0;   // its launch on the device, from the server's reference
     int state = REQ_PENDING;
     hz_status err = HZ_OK;
+};
+
+// A device block held by the server for reuse (request outputs) or to be
+// freed with the lock dropped.
+struct Block {
+    void *ptr = nullptr;
+    size_t bytes = 0;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t t_start = nullptr, t_stop = nullptr;   // dispatch timestamps of the batch's first and last kernel
     bool busy = false;
     std::vector<Request *> reqs;
     void *jobs = nullptr;       // device job table
@@ -81,6 +97,12 @@ struct Server {
     bool stop = false;
     hz_ticket next_id = 1;
     hz_status fatal = HZ_OK;
+    hipEvent_t t_ref = nullptr;        // device time origin of the batch timestamps
+    std::vector<Block> out_pool;       // released request outputs, by size class
+    uint64_t out_pool_bytes = 0;
+    std::vector<Block> to_free;        // device blocks the scheduler frees unlocked
+    std::vector<void *> to_free_host;  // pinned host blocks likewise
+    size_t trim_fields = 0;            // bytes of pooled (released) field memory to give back, unlocked
 };
 
 static double now_s()
@@ -110,17 +132,49 @@ static BatchKey make_key(const hz_field *f, const hz_step &st)
     return k;
 }
 
-static void free_outputs(Server *S, Request *r)
+// Output blocks come in size classes, four per octave from 64 KiB, so that a
+// released block serves later requests of similar size.
+static size_t out_class(int64_t bytes)
 {
-    if (r->out_mem) ctx_free(S->ctx, r->out_mem, (size_t)r->out_bytes);
-    r->out_mem = nullptr;
+    size_t p = (size_t)64 << 10;
+    while (p * 2 <= (size_t)bytes) p <<= 1;
+    for (size_t k = 0; k <= 4; ++k)
+        if ((size_t)bytes <= p + k * (p / 4)) return p + k * (p / 4);
+    return 2 * p;
 }
 
-// Allocate a request's outputs: one buffer carved into the five arrays.
+// Return a request's outputs to the pool (its batch has completed; the caller
+// has finished reading them).  Called with the server lock held.
+static void pool_outputs(Server *S, Request *r)
+{
+    if (r->out_mem) {
+        S->out_pool.push_back({r->out_mem, r->out_cap});
+        S->out_pool_bytes += r->out_cap;
+    }
+    r->out_mem = nullptr;
+    r->out_cap = 0;
+}
+
+// A request's outputs: one block of its size class, from the pool or newly
+// allocated (never by giving back other memory: that waits for the device).
+// Called with the server lock held.
 static hz_status alloc_outputs(Server *S, Request *r)
 {
-    hz_status st = ctx_alloc(S->ctx, &r->out_mem, (size_t)r->out_bytes);
-    if (st != HZ_OK) return st;
+    const size_t cls = out_class(r->out_bytes);
+    r->out_mem = nullptr;
+    for (size_t i = 0; i < S->out_pool.size(); ++i)
+        if (S->out_pool[i].bytes == cls) {
+            r->out_mem = S->out_pool[i].ptr;
+            S->out_pool_bytes -= cls;
+            S->out_pool[i] = S->out_pool.back();
+            S->out_pool.pop_back();
+            break;
+        }
+    if (!r->out_mem) {
+        hz_status st = ctx_alloc_nowait(S->ctx, &r->out_mem, cls);
+        if (st != HZ_OK) return st;
+    }
+    r->out_cap = cls;
     char *base = (char *)r->out_mem;
     const int64_t n = r->nrays;
     r->out.disp = (float *)base;
@@ -156,20 +210,24 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     }
     const size_t job_bytes = sizeof(TraceJob) * jobs.size();
     if (sl.jobs_cap < job_bytes) {
-        if (sl.jobs) ctx_free(S->ctx, sl.jobs, sl.jobs_cap);
-        sl.jobs = nullptr;
-        sl.jobs_cap = 0;
-        hz_status st = ctx_alloc(S->ctx, &sl.jobs, job_bytes);
+        // the slot is idle, so its old table is no longer read; it is freed
+        // later with the lock dropped
+        const size_t want = std::max(job_bytes, 2 * sl.jobs_cap);
+        void *p = nullptr;
+        hz_status st = ctx_alloc_nowait(S->ctx, &p, want);
         if (st != HZ_OK) return st;
-        sl.jobs_cap = job_bytes;
+        if (sl.jobs) S->to_free.push_back({sl.jobs, sl.jobs_cap});
+        sl.jobs = p;
+        sl.jobs_cap = want;
     }
     if (sl.pinned_cap < job_bytes) {
-        if (sl.pinned) (void)hipHostFree(sl.pinned);
-        sl.pinned = nullptr;
-        sl.pinned_cap = 0;
-        if (hipHostMalloc(&sl.pinned, job_bytes, hipHostMallocDefault) != hipSuccess)
+        const size_t want = std::max(job_bytes, 2 * sl.pinned_cap);
+        void *p = nullptr;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess)
             return set_error(HZ_E_NOMEM, "serve: hipHostMalloc failed");
-        sl.pinned_cap = job_bytes;
+        if (sl.pinned) S->to_free_host.push_back(sl.pinned);
+        sl.pinned = p;
+        sl.pinned_cap = want;
     }
     for (Request *r : batch) {
         hz_status st = field_ready(r->field, sl.stream);
@@ -197,15 +255,15 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.refill_min = 32;
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
-    const KTimer t = profile_timer(S->ctx, "serve_batch");
     const bool clear = !sl.counters_clean;
     sl.counters_clean = false;
-    if (launch_raygen(L, clear, sl.stream, KTimer{t.start, nullptr}) != hipSuccess ||
-        launch_march(dt, L, blocks, sl.stream, KTimer{nullptr, t.stop}) != hipSuccess)
+    // the dispatch packets of the first and last kernel record the batch's
+    // device start and end (no extra packets)
+    if (launch_raygen(L, clear, sl.stream, KTimer{sl.t_start, nullptr}) != hipSuccess ||
+        launch_march(dt, L, blocks, sl.stream, KTimer{nullptr, sl.t_stop}) != hipSuccess)
         return set_error(HZ_E_DEVICE, "serve: trace launch failed");
     sl.counter_set = 1 - sl.counter_set;
     sl.counters_clean = true;
-    profile_commit(S->ctx, "serve_batch", t);
     if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return set_error(HZ_E_DEVICE, "serve: hipEventRecord");
     CallMark done;
     hz_status st = ctx_mark(S->ctx, sl.stream, &done);
@@ -219,6 +277,24 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     return HZ_OK;
 }
 
+// Free the blocks queued for freeing, with the server lock dropped (freeing
+// device memory waits for the device).
+static void free_deferred(Server *S, std::unique_lock<std::mutex> &lk)
+{
+    if (S->to_free.empty() && S->to_free_host.empty() && !S->trim_fields) return;
+    std::vector<Block> dev;
+    std::vector<void *> host;
+    dev.swap(S->to_free);
+    host.swap(S->to_free_host);
+    const size_t trim = S->trim_fields;
+    S->trim_fields = 0;
+    lk.unlock();
+    for (const Block &b : dev) ctx_free(S->ctx, b.ptr, b.bytes);
+    for (void *h : host) (void)hipHostFree(h);
+    if (trim) ctx_trim_pool(S->ctx, trim);
+    lk.lock();
+}
+
 static void scheduler(Server *S)
 {
     (void)hipSetDevice(ctx_device(S->ctx));
@@ -230,8 +306,14 @@ static void scheduler(Server *S)
             const hipError_t e = hipEventQuery(sl.done);
             if (e == hipSuccess || e != hipErrorNotReady) {
                 const double t = now_s();
+                float ms0 = 0.0f, ms1 = 0.0f;
+                if (e == hipSuccess && hipEventElapsedTime(&ms0, S->t_ref, sl.t_start) == hipSuccess &&
+                    hipEventElapsedTime(&ms1, S->t_ref, sl.t_stop) == hipSuccess)
+                    profile_add(S->ctx, "serve_batch", (double)(ms1 - ms0));
                 for (Request *r : sl.reqs) {
                     r->t_done = t;
+                    r->dev_start_ms = ms0;
+                    r->dev_end_ms = ms1;
                     r->state = e == hipSuccess ? REQ_DONE : REQ_FAILED;
                     if (e != hipSuccess) r->err = HZ_E_DEVICE;
                 }
@@ -247,9 +329,11 @@ static void scheduler(Server *S)
             std::vector<PendingInfo> info;
             const size_t window = std::min<size_t>(S->pending.size(), 256);
             for (size_t i = 0; i < window; ++i)
-                info.push_back({S->pending[i]->key, S->pending[i]->nslots, S->pending[i]->out_bytes});
+                info.push_back({S->pending[i]->key, S->pending[i]->nslots, (int64_t)out_class(S->pending[i]->out_bytes)});
+            // pooled output blocks count as free memory: they are reused, or
+            // given back when an allocation finds the budget short
             const std::vector<size_t> pick =
-                plan_batch(info, S->slot_capacity, (int64_t)ctx_mem_avail(S->ctx), 256);
+                plan_batch(info, S->slot_capacity, (int64_t)(ctx_mem_avail(S->ctx) + S->out_pool_bytes), 256);
             if (pick.empty()) {
                 // the oldest request waits for memory; when stopping with nothing
                 // running, no memory will come back: fail what is left
@@ -264,10 +348,24 @@ static void scheduler(Server *S)
                 break;
             }
             std::vector<Request *> batch;
+            bool short_mem = false;
             for (size_t i : pick) {
                 Request *r = S->pending[i];
-                if (alloc_outputs(S, r) != HZ_OK) break;   // memory went away: launch what we have
+                if (alloc_outputs(S, r) != HZ_OK) {   // memory went away: launch what we have
+                    short_mem = true;
+                    break;
+                }
                 batch.push_back(r);
+            }
+            if (short_mem) {
+                // pooled output blocks of other sizes, or released fields,
+                // hold the budget: give them back (below, unlocked); the rest
+                // waits for the next round
+                S->to_free.insert(S->to_free.end(), S->out_pool.begin(), S->out_pool.end());
+                S->out_pool.clear();
+                S->out_pool_bytes = 0;
+                S->trim_fields = (size_t)out_class(S->pending[pick[batch.size()]]->out_bytes);
+                progressed = progressed || !S->to_free.empty();
             }
             if (batch.empty()) break;
             // remove the launched requests from the pending queue (keep order of the rest)
@@ -287,6 +385,7 @@ static void scheduler(Server *S)
             }
             progressed = true;
         }
+        free_deferred(S, lk);
         if (S->stop && S->pending.empty() && !any_busy) break;
         if (!progressed) S->cv.wait_for(lk, any_busy ? std::chrono::microseconds(20) : std::chrono::milliseconds(2));
     }
@@ -309,12 +408,18 @@ void server_destroy(Server *S)
         if (sl.counters) ctx_free(S->ctx, sl.counters, kCounterBytes);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.t_start) (void)hipEventDestroy(sl.t_start);
+        if (sl.t_stop) (void)hipEventDestroy(sl.t_stop);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     for (auto &kv : S->reqs) {
-        free_outputs(S, kv.second);
+        pool_outputs(S, kv.second);
         delete kv.second;
     }
+    for (const Block &b : S->out_pool) ctx_free(S->ctx, b.ptr, b.bytes);
+    for (const Block &b : S->to_free) ctx_free(S->ctx, b.ptr, b.bytes);
+    for (void *h : S->to_free_host) (void)hipHostFree(h);
+    if (S->t_ref) (void)hipEventDestroy(S->t_ref);
     delete S;
 }
 
@@ -341,12 +446,18 @@ extern "C" hz_status hz_server_start(hz_ctx *c, int32_t nslots, int64_t max_batc
         if (st == HZ_OK) st = ctx_alloc(c, &sl.counters, kCounterBytes);
         if (st == HZ_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess)
             st = set_error(HZ_E_DEVICE, "hz_server_start: hipStreamCreate failed");
-        if (st == HZ_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+        if (st == HZ_OK && (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+                            hipEventCreate(&sl.t_start) != hipSuccess || hipEventCreate(&sl.t_stop) != hipSuccess))
             st = set_error(HZ_E_DEVICE, "hz_server_start: hipEventCreate failed");
         if (st != HZ_OK) {
             server_destroy(S);
             return st;
         }
+    }
+    if (hipEventCreate(&S->t_ref) != hipSuccess || hipEventRecord(S->t_ref, S->slots[0].stream) != hipSuccess ||
+        hipEventSynchronize(S->t_ref) != hipSuccess) {
+        server_destroy(S);
+        return set_error(HZ_E_DEVICE, "hz_server_start: reference event failed");
     }
     ctx_server(c) = S;
     S->th = std::thread(scheduler, S);
@@ -374,6 +485,8 @@ extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *view
     if (nviews < 1 || nviews > 4096) return set_error(HZ_E_INVALID, "hz_submit: nviews outside [1, 4096]");
     hz_status st = check_step(step, fn);
     if (st != HZ_OK) return st;
+    st = field_usable(c, f, fn);
+    if (st != HZ_OK) return st;
     Request *r = new Request();
     r->field = const_cast<hz_field *>(f);
     r->views.assign(views, views + nviews);
@@ -392,7 +505,7 @@ extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *view
     r->key = make_key(f, *step);
     uint64_t budget = 0;
     hz_ctx_memory(c, nullptr, &budget);
-    if (r->nslots > S->slot_capacity || (uint64_t)r->out_bytes > budget) {
+    if (r->nslots > S->slot_capacity || (uint64_t)out_class(r->out_bytes) > budget) {
         delete r;
         return set_error(HZ_E_BUDGET, "hz_submit: the request exceeds the batch capacity or the HBM budget");
     }
@@ -438,6 +551,21 @@ extern "C" hz_status hz_request_outputs(hz_ctx *c, hz_ticket t, hz_trace_out *ou
     return HZ_OK;
 }
 
+extern "C" hz_status hz_request_timing(hz_ctx *c, hz_ticket t, double *device_start_ms, double *device_end_ms)
+{
+    if (!c) return set_error(HZ_E_INVALID, "hz_request_timing: ctx is NULL");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_request_timing: no server running");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return set_error(HZ_E_NOTFOUND, "hz_request_timing: unknown ticket");
+    const Request *r = it->second;
+    if (r->state != REQ_DONE) return set_error(HZ_E_INVALID, "hz_request_timing: the request is not complete");
+    if (device_start_ms) *device_start_ms = r->dev_start_ms;
+    if (device_end_ms) *device_end_ms = r->dev_end_ms;
+    return HZ_OK;
+}
+
 extern "C" hz_status hz_request_release(hz_ctx *c, hz_ticket t)
 {
     if (!c) return set_error(HZ_E_INVALID, "hz_request_release: ctx is NULL");
@@ -450,10 +578,10 @@ extern "C" hz_status hz_request_release(hz_ctx *c, hz_ticket t)
         Request *r = it->second;
         if (r->state == REQ_RUNNING) return set_error(HZ_E_INVALID, "hz_request_release: the request is running");
         if (r->state == REQ_PENDING) S->pending.erase(std::find(S->pending.begin(), S->pending.end(), r));
-        free_outputs(S, r);
+        pool_outputs(S, r);
         S->reqs.erase(it);
         delete r;
     }
-    S->cv.notify_all();   // freed memory may admit a waiting request
+    S->cv.notify_all();   // returned memory may admit a waiting request
     return HZ_OK;
 }

@@ -58,9 +58,11 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
                                                     uint32_t *__restrict__ lrank, uint32_t *__restrict__ count,
-                                                    uint32_t *__restrict__ mmax)
+                                                    uint32_t *__restrict__ mmax, uint32_t *__restrict__ fail)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // the call's scan-failure word starts clear (the scan runs after this launch)
+    if (i == 0) *fail = 0u;
     uint32_t mbits = 0u;
     if (i < n) {
         const int cx = cell_coord(x[i], cg.clo[0], cg.inv_cell, cg.nc[0]);
@@ -99,7 +101,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_PER_THREAD;
 constexpr int SCAN_ONEPASS_TILES = 1024;
-constexpr size_t SCAN_TAG_OFFSET = 256;   // bytes: the ticket counter, then the tile tags
+constexpr size_t SCAN_TAG_OFFSET = 256;   // bytes: ticket counter and failure word, then tile tags or sums
 
 // Inclusive scan of one value per thread across a 256-thread workgroup.
 __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *wave_tot)
@@ -181,12 +183,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(uint32_t *__restric
 // value at launch), publish their tile's sum tagged with their ticket, and add
 // the sums of all lower tiles.  Each lower tile belongs to a workgroup that
 // took its ticket earlier and is therefore already running, and it waits only
-// on tiles lower still, so every wait ends.  (The bound on the spin is a
-// guard, never reached.)
+// on tiles lower still, so every wait ends.  The spin is still bounded
+// (spin_limit sleeps per lower tile): a wait that gives up adds nothing,
+// sets the call's failure word `fail` (the later kernels of the call then
+// skip their work and leave NaN in the field) and stores `serial` into the
+// host-visible word `fail_host`, where the library finds it.  tag_bias is 0
+// except in the fault test, where it makes every wait give up.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_onepass(uint32_t *__restrict__ count, int32_t n,
                                                                int32_t ntiles, uint32_t *__restrict__ ticket_ctr,
                                                                uint64_t *__restrict__ tags, uint32_t base,
-                                                               uint32_t *__restrict__ start)
+                                                               uint32_t *__restrict__ start, uint32_t spin_limit,
+                                                               uint32_t tag_bias, uint32_t *__restrict__ fail,
+                                                               uint32_t *fail_host, uint32_t serial)
 {
     __shared__ uint32_t wt[4];
     __shared__ uint32_t sh_ticket;
@@ -214,15 +222,24 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_onepass(uint32_t *__restr
         __hip_atomic_store(&tags[tile], ((uint64_t)(ticket + 1u) << 32) | incl, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     uint32_t lower = 0;
+    bool gave_up = false;
     for (int32_t t = (int32_t)threadIdx.x; t < tile; t += SCAN_THREADS) {
-        const uint32_t want = base + (uint32_t)t + 1u;
-        uint64_t w = 0;
-        for (uint32_t spin = 0; spin < (1u << 26); ++spin) {
-            w = __hip_atomic_load(&tags[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((uint32_t)(w >> 32) == want) break;
+        const uint32_t want = base + (uint32_t)t + 1u + tag_bias;
+        bool got = false;
+        for (uint32_t spin = 0; spin < spin_limit; ++spin) {
+            const uint64_t w = __hip_atomic_load(&tags[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((uint32_t)(w >> 32) == want) {
+                lower += (uint32_t)w;
+                got = true;
+                break;
+            }
             __builtin_amdgcn_s_sleep(1);
         }
-        lower += (uint32_t)w;
+        gave_up = gave_up || !got;
+    }
+    if (gave_up) {
+        __hip_atomic_store(fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (fail_host) __hip_atomic_store(fail_host, serial, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lower += (uint32_t)__shfl_xor((int)lower, off);
@@ -238,14 +255,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_onepass(uint32_t *__restr
     if (tile == ntiles - 1 && threadIdx.x == SCAN_THREADS - 1) start[n] = run;
 }
 
-// Every binned particle takes the slot of its cell given by its arrival rank.
+// Every binned particle takes the slot of its cell given by its arrival rank
+// (nothing when the scan failed: the starts are then wrong).
 __global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict__ cid,
                                                       const uint32_t *__restrict__ lrank, int32_t n,
                                                       const uint32_t *__restrict__ start,
-                                                      uint32_t *__restrict__ slots)
+                                                      uint32_t *__restrict__ slots, const uint32_t *__restrict__ fail)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || *fail) return;
     uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
     slots[start[c] + lrank[i]] = (uint32_t)i;
@@ -259,10 +277,10 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
                                                     const uint32_t *__restrict__ slots, int32_t n,
                                                     const float *__restrict__ x, const float *__restrict__ y,
                                                     const float *__restrict__ z, const float *__restrict__ m,
-                                                    float4 *__restrict__ sorted)
+                                                    float4 *__restrict__ sorted, const uint32_t *__restrict__ fail)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || *fail) return;
     const uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
     const uint32_t b = start[c], e = start[c + 1];
@@ -369,7 +387,8 @@ constexpr int SPLAT_WAVES = 4;
 template <int BZ>
 __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
                                                             const float4 *__restrict__ parts, int32_t nbricks,
-                                                            int32_t per_xcd, float *__restrict__ dn)
+                                                            int32_t per_xcd, float *__restrict__ dn,
+                                                            const uint32_t *__restrict__ fail)
 {
     __shared__ float partial[SPLAT_WAVES - 1][BZ][64];
     const int32_t brick = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
@@ -410,8 +429,10 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
 #pragma unroll
     for (int v = 0; v < BZ; ++v) acc[v] = 0.0f;
     // rows (kz, ky) in order, every SPLAT_WAVES-th from the wave's index (no rows
-    // if the y range is empty, so the row stepping below always advances)
-    int kz = ny >= 1 ? cz0 : cz1 + 1, ky = cy0 + wave;
+    // if the y range is empty, so the row stepping below always advances); no
+    // rows, and NaN voxels, when the cell-list scan failed
+    const bool bad = *fail != 0u;
+    int kz = ny >= 1 && !bad ? cz0 : cz1 + 1, ky = cy0 + wave;
     for (;;) {
         while (ky > cy1) {
             ky -= ny;
@@ -463,7 +484,7 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     }
     __syncthreads();
     if (wave == 0 && vx < P.res[0] && vy < P.res[1]) {
-        const float sc = 0.25f * P.scale;
+        const float sc = bad ? __builtin_nanf("") : 0.25f * P.scale;
 #pragma unroll
         for (int v = 0; v < BZ; ++v) {
             float sum = acc[v];
@@ -494,7 +515,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_splat_scatter(SplatParams P, con
                                                               const float4 *__restrict__ parts,
                                                               const uint32_t *__restrict__ mmax_bits,
                                                               int32_t ntx, int32_t nty, int32_t ntiles,
-                                                              int32_t per_xcd, float *__restrict__ dn)
+                                                              int32_t per_xcd, float *__restrict__ dn,
+                                                              const uint32_t *__restrict__ fail)
 {
     __shared__ unsigned long long acc[SC_TX * SC_TY * SC_TZ];
     __shared__ uint32_t row_first[SC_MAXROWS];
@@ -514,6 +536,14 @@ __global__ __launch_bounds__(SC_THREADS) void k_splat_scatter(SplatParams P, con
         bhi[a] = P.lo[a] + ((float)(o[a] + nt[a] - 1) + 0.5f) * P.sp[a];
     }
     for (int v = threadIdx.x; v < SC_TX * SC_TY * SC_TZ; v += SC_THREADS) acc[v] = 0ull;
+    if (*fail) {   // the cell-list scan failed: NaN voxels, no particle reads
+        for (int v = threadIdx.x; v < SC_TX * SC_TY * SC_TZ; v += SC_THREADS) {
+            const int li = v % SC_TX, lj = (v / SC_TX) % SC_TY, lk = v / (SC_TX * SC_TY);
+            if (li < nt[0] && lj < nt[1] && lk < nt[2])
+                dn[((int64_t)(o[2] + lk) * P.res[1] + (o[1] + lj)) * P.res[0] + (o[0] + li)] = __builtin_nanf("");
+        }
+        return;
+    }
 
     // cell rows (ky, kz) and x-range of cells overlapping the grown tile (one
     // cell of slack absorbs rounding)
@@ -626,14 +656,15 @@ int scatter_max_rows(const SplatParams &P)
 int scatter_rows_limit() { return SC_MAXROWS; }
 
 hipError_t launch_splat_scatter(const SplatParams &P, const uint32_t *start, const float4 *sorted,
-                                const uint32_t *mmax_bits, float *dn, hipStream_t s, const KTimer &t)
+                                const uint32_t *mmax_bits, float *dn, const uint32_t *fail, hipStream_t s,
+                                const KTimer &t)
 {
     const int32_t ntx = (P.res[0] + SC_TX - 1) / SC_TX, nty = (P.res[1] + SC_TY - 1) / SC_TY,
                   ntz = (P.res[2] + SC_TZ - 1) / SC_TZ;
     const int32_t ntiles = ntx * nty * ntz;
     const int32_t per_xcd = (ntiles + 7) / 8;
     hipExtLaunchKernelGGL(k_splat_scatter, dim3((unsigned)(per_xcd * 8)), dim3(SC_THREADS), 0, s, t.start, t.stop, 0,
-                          P, start, sorted, mmax_bits, ntx, nty, ntiles, per_xcd, dn);
+                          P, start, sorted, mmax_bits, ntx, nty, ntiles, per_xcd, dn, fail);
     return hipGetLastError();
 }
 
@@ -753,15 +784,22 @@ size_t scan_scratch_bytes(int32_t ncells) { return SCAN_TAG_OFFSET + 8u * (size_
 
 bool scan_is_onepass(int32_t ncells) { return scan_tiles(ncells) <= SCAN_ONEPASS_TILES; }
 
+uint32_t *scan_fail_word(void *scan) { return (uint32_t *)scan + 1; }
+
 hipError_t launch_cell_list(const float *x, const float *y, const float *z, const float *m, int32_t n,
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, int64_t count_clear_words,
                             uint32_t *start, uint32_t *lrank, uint32_t *slots, float4 *sorted, void *scan,
-                            bool scan_reset, uint32_t *scan_base, bool want_mmax, hipStream_t s, const KTimer &t)
+                            bool scan_reset, uint32_t *scan_base, bool want_mmax, const ScanGuard &guard,
+                            hipStream_t s, const KTimer &t)
 {
-    // The counts must start at zero; each scan leaves them so.  count[ncells+1]
-    // holds max |m| (scatter splat only), which the caller clears through
-    // count_clear_words.  The scan scratch starts with the one-pass scan's
-    // ticket counter, then the tile tags (both cleared by scan_reset).
+    // The counts must start at zero; each scan leaves them so.
+    // count[ncells+1] holds max |m| (scatter splat only), which the caller
+    // clears through count_clear_words.  The scan scratch holds the one-pass
+    // scan's ticket counter (word 0), the call's scan-failure word (word 1,
+    // cleared by k_cell_count), and from byte SCAN_TAG_OFFSET the tile tags of
+    // the one-pass scan (cleared with the counter by scan_reset) or the tile
+    // sums of the three-pass one.
+    uint32_t *fail = scan_fail_word(scan);
     const int32_t ntiles = scan_tiles(cg.ncells);
     const bool onepass = ntiles <= SCAN_ONEPASS_TILES;
     bool first = true;
@@ -780,17 +818,18 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     if (want_mmax)
         hipExtLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1);
+                              count + cg.ncells + 1, fail);
     else
         hipExtLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1);
+                              count + cg.ncells + 1, fail);
     if (onepass) {
         hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, ntiles,
-                           (uint32_t *)scan, (uint64_t *)((char *)scan + SCAN_TAG_OFFSET), *scan_base, start);
+                           (uint32_t *)scan, (uint64_t *)((char *)scan + SCAN_TAG_OFFSET), *scan_base, start,
+                           guard.spin_limit, guard.tag_bias, fail, guard.fail_host, guard.serial);
         *scan_base += (uint32_t)ntiles;
     } else {
-        uint32_t *tile_sum = (uint32_t *)scan;
+        uint32_t *tile_sum = (uint32_t *)((char *)scan + SCAN_TAG_OFFSET);
         hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells,
                            tile_sum);
         hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(SCAN_THREADS), 0, s, tile_sum, ntiles,
@@ -798,22 +837,25 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells,
                            tile_sum, start);
     }
-    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots,
+                       fail);
     hipExtLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, nullptr, t.stop, 0, cid, start,
-                          slots, n, x, y, z, m, sorted);
+                          slots, n, x, y, z, m, sorted, fail);
     return hipGetLastError();
 }
 
-hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn, hipStream_t s,
-                        const KTimer &t)
+hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn,
+                        const uint32_t *fail, hipStream_t s, const KTimer &t)
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
     const int32_t per_xcd = (nbricks + 7) / 8;
     const dim3 g((unsigned)(per_xcd * 8)), b(64 * SPLAT_WAVES);
     if (P.bz == 8)
-        hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn);
+        hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn,
+                              fail);
     else
-        hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn);
+        hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn,
+                              fail);
     return hipGetLastError();
 }
 

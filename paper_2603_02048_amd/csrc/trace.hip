@@ -32,6 +32,7 @@
 // |p| ds/n P g to p reproduces Eq. 16 exactly while dw keeps the low-order bits
 // of many small turns that a unit vector would round away.
 #include "haze_device.h"
+#include "ray_geom.h"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
@@ -90,40 +91,6 @@ __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, 
     return r.p < J.width && r.q < J.height;
 }
 
-__device__ __forceinline__ float3 pixel_dir(const TraceJob &J, int32_t p, int32_t q)
-{
-    const float sx = (float)p + 0.5f - J.half_w;
-    const float sy = (float)q + 0.5f - J.half_h;
-    float dx = J.fpx * J.f[0] + sx * J.r[0] - sy * J.u[0];
-    float dy = J.fpx * J.f[1] + sx * J.r[1] - sy * J.u[1];
-    float dz = J.fpx * J.f[2] + sx * J.r[2] - sy * J.u[2];
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-    return make_float3(dx * inv, dy * inv, dz * inv);
-}
-
-// Slab test; on a hit returns the entry parameter clamped at 0 (and the exit
-// parameter in t1 when asked).
-__device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3], const float d[3], float &t0,
-                                             float *t1 = nullptr)
-{
-    float a = -INFINITY, b = INFINITY;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (d[k] == 0.0f) {
-            if (o[k] < G.lo[k] || o[k] > G.hi[k]) return false;
-            continue;
-        }
-        const float inv = 1.0f / d[k];
-        float t1 = (G.lo[k] - o[k]) * inv, t2 = (G.hi[k] - o[k]) * inv;
-        a = fmaxf(a, fminf(t1, t2));
-        b = fminf(b, fmaxf(t1, t2));
-    }
-    if (a > b || b <= 0.0f) return false;
-    t0 = fmaxf(a, 0.0f);
-    if (t1) *t1 = b;
-    return true;
-}
-
 // Exit distance along w from a point in the volume (clamped at 0).
 __device__ __forceinline__ float exit_distance(const TraceGrid &G, const float c[3], const float w[3])
 {
@@ -174,15 +141,142 @@ __device__ __forceinline__ int cast_quads(const TraceLaunch &L, const float x[3]
     return best;
 }
 
+// ---- triangle-mesh scenes ----
+
+__device__ __forceinline__ bool in_tri(const SceneQuad &T, const float h[3])
+{
+    const float u = fmaf(T.du[0], h[0], fmaf(T.du[1], h[1], fmaf(T.du[2], h[2], -T.du0)));
+    const float v = fmaf(T.dv[0], h[0], fmaf(T.dv[1], h[1], fmaf(T.dv[2], h[2], -T.dv0)));
+    return u >= 0.0f && v >= 0.0f && u + v <= 1.0f;
+}
+
+// Straight ray x + t w against triangle k: keeps the first hit in (best, bt),
+// ties to the lower triangle index.
+__device__ __forceinline__ void cast_tri(const MeshLaunch &M, int k, const float x[3], const float w[3], int &best,
+                                         float &bt)
+{
+    const SceneQuad &T = M.tris[k];
+    const float dn = T.n[0] * w[0] + T.n[1] * w[1] + T.n[2] * w[2];
+    if (dn == 0.0f) return;
+    const float t = -quad_side(T, x) / dn;
+    if (!(t >= 0.0f) || t > bt || (t == bt && best >= 0 && k >= best)) return;
+    const float h[3] = {fmaf(t, w[0], x[0]), fmaf(t, w[1], x[1]), fmaf(t, w[2], x[2])};
+    if (!in_tri(T, h)) return;
+    best = k;
+    bt = t;
+}
+
+// First triangle met by the straight ray x + t w, t in [0, tmax]: the ray
+// walks the shell cells it crosses (3D DDA) and tests their lists, until the
+// next cell starts beyond the best hit.  A cell lists every triangle within
+// reach of it, so a hit inside a cell is found there whatever the rounding of
+// the walk.  Returns the triangle or -1, and t; counts the exact tests.
+__device__ int cast_mesh(const MeshLaunch &M, const float x[3], const float w[3], float tmax, float &thit,
+                         uint32_t &ntests)
+{
+    int best = -1;
+    float bt = tmax;
+    if (M.brute) {
+        for (int k = 0; k < M.ntris; ++k) cast_tri(M, k, x, w, best, bt);
+        ntests += (uint32_t)M.ntris;
+        thit = bt;
+        return best;
+    }
+    float ta = 0.0f, tb = tmax;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float lo = M.lo[a], hi = M.lo[a] + (float)M.res[a] * M.cell;
+        if (w[a] == 0.0f) {
+            if (x[a] < lo || x[a] > hi) ta = INFINITY;
+            continue;
+        }
+        const float inv = 1.0f / w[a];
+        const float t1 = (lo - x[a]) * inv, t2 = (hi - x[a]) * inv;
+        ta = fmaxf(ta, fminf(t1, t2));
+        tb = fminf(tb, fmaxf(t1, t2));
+    }
+    if (!(ta <= tb)) {
+        thit = bt;
+        return -1;
+    }
+    int ci[3], stp[3];
+    float tn[3], td[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float p = fmaf(ta, w[a], x[a]);
+        ci[a] = min(max((int)floorf((p - M.lo[a]) * M.inv_cell), 0), M.res[a] - 1);
+        if (w[a] > 0.0f) {
+            stp[a] = 1;
+            tn[a] = (M.lo[a] + (float)(ci[a] + 1) * M.cell - x[a]) / w[a];
+            td[a] = M.cell / w[a];
+        } else if (w[a] < 0.0f) {
+            stp[a] = -1;
+            tn[a] = (M.lo[a] + (float)ci[a] * M.cell - x[a]) / w[a];
+            td[a] = -M.cell / w[a];
+        } else {
+            stp[a] = 0;
+            tn[a] = INFINITY;
+            td[a] = INFINITY;
+        }
+    }
+    float tenter = ta;
+    for (int it = 0; it < M.res[0] + M.res[1] + M.res[2] + 3; ++it) {
+        if (tenter > bt) break;
+        const uint32_t cell = ((uint32_t)ci[2] * (uint32_t)M.res[1] + (uint32_t)ci[1]) * (uint32_t)M.res[0] +
+                              (uint32_t)ci[0];
+        const uint32_t e0 = M.start[cell], e1 = M.start[cell + 1];
+        for (uint32_t e = e0; e < e1; ++e) cast_tri(M, (int)M.list[e], x, w, best, bt);
+        ntests += e1 - e0;
+        const int a = tn[0] <= tn[1] ? (tn[0] <= tn[2] ? 0 : 2) : (tn[1] <= tn[2] ? 1 : 2);
+        tenter = tn[a];
+        if (tenter > tb) break;
+        ci[a] += stp[a];
+        if (ci[a] < 0 || ci[a] >= M.res[a]) break;
+        tn[a] += td[a];
+    }
+    thit = bt;
+    return best;
+}
+
+// The chord a -> b = a + ds w of one march step against triangle k: the side
+// value changes sign (or reaches zero) along it; keeps the first crossing
+// (fraction lam, then the lower index) in (best, bl, hp).
+__device__ __forceinline__ void chord_tri(const MeshLaunch &M, int k, const float a[3], const float b[3],
+                                          const float w[3], float ds, int &best, float &bl, float hp[3])
+{
+    const SceneQuad &T = M.tris[k];
+    const float s0 = quad_side(T, a), s1 = quad_side(T, b);
+    if (s0 == 0.0f || (s0 > 0.0f && s1 > 0.0f) || (s0 < 0.0f && s1 < 0.0f)) return;
+    const float lam = s0 / (s0 - s1);
+    if (!(lam < bl || (lam == bl && k < best))) return;
+    const float back = (1.0f - lam) * ds;
+    const float h[3] = {fmaf(-back, w[0], b[0]), fmaf(-back, w[1], b[1]), fmaf(-back, w[2], b[2])};
+    if (!in_tri(T, h)) return;
+    best = k;
+    bl = lam;
+    hp[0] = h[0]; hp[1] = h[1]; hp[2] = h[2];
+}
+
 // Writes a finished ray.  With surf >= 0 the ray already met scene board surf
 // at hp; otherwise the straight ray (x, w) is cast against the boards and the
 // view's backdrop plane (front side only) and the nearest wins, boards on
 // ties.  The image point is re-projected through the pinhole: displacement =
 // projected point - pixel centre (Sec. 3.3.2).
-template <bool BOARDS>
-__device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, const float x[3], const float w[3],
-                                           uint32_t steps, int status, const float *hp = nullptr, int surf = -1)
+// Per-ray count of exact triangle tests of the ray's output, or null.
+__device__ __forceinline__ uint32_t *tri_tests_of(const TraceLaunch &L, const Ray &r)
 {
+    return L.subset ? L.flat.tri_tests : L.jobs[r.job].tri_tests;
+}
+
+// SCENE 0: no scene; 1, 2: boards (surf is a board); 3: triangle mesh (surf
+// is a triangle, reported by its surface id, and ntests counts the exact
+// triangle tests the ray took so far).
+template <int SCENE>
+__device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, const float x[3], const float w[3],
+                                           uint32_t steps, int status, const float *hp = nullptr, int surf = -1,
+                                           uint32_t ntests = 0u)
+{
+    constexpr bool BOARDS = SCENE == 1 || SCENE == 2;
     const TraceJob &J = L.jobs[r.job];
     float disp0 = __builtin_nanf(""), disp1 = __builtin_nanf("");
     int sid = 255;
@@ -191,7 +285,7 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
         bool hit = surf >= 0;
         if (hit) {
             h[0] = hp[0]; h[1] = hp[1]; h[2] = hp[2];
-            sid = surf + 1;
+            sid = (SCENE == 3 ? (int)L.mesh.surf[surf] : surf) + 1;
         } else {
             const float denom = w[0] * J.plane_n[0] + w[1] * J.plane_n[1] + w[2] * J.plane_n[2];
             float tb = -1.0f;
@@ -210,6 +304,15 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
                     t = tq;
                     hit = true;
                     sid = q + 1;
+                }
+            }
+            if (SCENE == 3) {
+                float tq;
+                const int q = cast_mesh(L.mesh, x, w, hit ? tb : INFINITY, tq, ntests);
+                if (q >= 0) {
+                    t = tq;
+                    hit = true;
+                    sid = (int)L.mesh.surf[q] + 1;
                 }
             }
             if (hit) {
@@ -237,17 +340,19 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
         }
     }
     float *disp, *ep, *ed;
-    uint32_t *st;
+    uint32_t *st, *tt;
     uint8_t *stat, *sf;
     if (L.subset) {
         disp = L.flat.disp; ep = L.flat.exit_pos; ed = L.flat.exit_dir; st = L.flat.steps; stat = L.flat.status;
-        sf = L.flat.surface;
+        sf = L.flat.surface; tt = L.flat.tri_tests;
     } else {
         disp = J.disp; ep = J.exit_pos; ed = J.exit_dir; st = J.steps; stat = J.status; sf = J.surface;
+        tt = J.tri_tests;
     }
     if (BOARDS || sf) {
         if (sf) sf[r.out] = (uint8_t)sid;
     }
+    if (SCENE == 3 && tt) tt[r.out] = ntests;   // the whole ray's exact triangle tests
     const int64_t o = r.out;
     if (disp) {
         disp[2 * o] = disp0;
@@ -295,6 +400,9 @@ __device__ __forceinline__ uint32_t bin_rank(int bin, uint32_t (*wcnt)[kRayBins]
     return rank;
 }
 
+// SCENE: 0 no scene, 1 boards, 3 triangle mesh (the launch's scene kind, so
+// that the common case carries no scene code).
+template <int SCENE>
 __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,20 +417,34 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
             float t0, t1 = 0.0f;
             enters = enter_volume(L.grid, J.eye, d, t0, &t1);
             if (enters) bin = kRayBins - 1 - min(kRayBins - 1, max(0, (int)((t1 - t0) * L.inv_len_bin)));
-            if (enters && L.nquads > 0) {
+            if (SCENE == 3) {
+                if (enters) {
+                    // the mesh in front of the volume ends the ray before it enters;
+                    // otherwise the march continues the test count from here
+                    float tq;
+                    uint32_t nt = 0u;
+                    const int q = cast_mesh(L.mesh, J.eye, d, t0, tq, nt);
+                    if (q >= 0) {
+                        const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
+                        finish_ray<3>(L, r, J.eye, d, 0u, 0, hp, q, nt);
+                        enters = false;
+                    } else if (uint32_t *tt = tri_tests_of(L, r)) {
+                        tt[r.out] = nt;
+                    }
+                } else {
+                    finish_ray<3>(L, r, J.eye, d, 0u, 0);
+                }
+            } else if (SCENE == 1 && enters) {
                 // a board in front of the volume ends the ray before it enters
                 float tq;
                 const int q = cast_quads(L, J.eye, d, t0, tq);
                 if (q >= 0) {
                     const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
-                    finish_ray<true>(L, r, J.eye, d, 0u, 0, hp, q);
+                    finish_ray<1>(L, r, J.eye, d, 0u, 0, hp, q);
                     enters = false;
                 }
             } else if (!enters) {
-                if (L.nquads > 0)
-                    finish_ray<true>(L, r, J.eye, d, 0u, 0);
-                else
-                    finish_ray<false>(L, r, J.eye, d, 0u, 0);
+                finish_ray<SCENE == 1 ? 1 : 0>(L, r, J.eye, d, 0u, 0);
             }
         } else if (L.subset) {
             // ray id outside the views: flag it, leave no stale values behind
@@ -335,6 +457,7 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
             if (L.flat.steps) L.flat.steps[slot] = 0u;
             if (L.flat.status) L.flat.status[slot] = 4u;
             if (L.flat.surface) L.flat.surface[slot] = 255u;
+            if (L.flat.tri_tests) L.flat.tri_tests[slot] = 0u;
         }
     }
     // the next launch's counter set (this launch's march uses the other one)
@@ -390,12 +513,11 @@ __device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
     v.w = fmaf(wgt, c.w, v.w);
 }
 
-// Trilinear (delta_n, g) at x: cell index clamped to [0, R-2], so the outer
-// half-voxel extrapolates linearly.
-template <int DT>
-// (Fields hold fewer than 2^31 voxels, checked on the host: 32-bit indices.
-// A NaN coordinate converts to cell 0 and poisons the weights, which the
-// march's finiteness test catches.)
+// Cell of x and the trilinear weights in it: cell index clamped to [0, R-2],
+// so the outer half-voxel extrapolates linearly.  (Fields hold fewer than
+// 2^31 voxels, checked on the host: 32-bit indices.  A NaN coordinate
+// converts to cell 0 and poisons the weights, which the march's finiteness
+// test catches.)
 __device__ __forceinline__ void cell_of(const TraceGrid &G, const float x[3], uint32_t &b, float t[3])
 {
     uint32_t i[3];
@@ -451,7 +573,7 @@ __device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *_
 {
     uint32_t b;
     float t[3];
-    cell_of<DT>(G, x, b, t);
+    cell_of(G, x, b, t);
     const uint32_t sy = (uint32_t)G.res[0], sz = (uint32_t)G.res[0] * (uint32_t)G.res[1];
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
     // Addresses by 64-bit pointer steps from the corner voxel: the x-neighbour
@@ -569,14 +691,19 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
     // only when the wave refills or stops, so the output code runs once for
     // all lanes finished since, not once per finishing lane.
     int fin = -1;        // status of a finished ray not yet written (-1: none)
-    int fin_surf = -1;   // its board (c is then the hit point), -1 for none
+    int fin_surf = -1;   // its board or triangle (c is then the hit point), -1 for none
+    uint32_t ntests = 0u;   // SCENE 3: the ray's exact triangle tests so far
 
+    // Outer loop: refill the wave's idle lanes (wave-uniform bookkeeping);
+    // inner loop: step the active lanes until enough of them have finished.
+    // The refill and the step are separate loops, so the step loop carries
+    // the rays' state alone (no joins with the refill code on every step).
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const uint32_t nidle = (uint32_t)__popcll(idle);
-        if (!done && (nidle >= refill_min || idle == ~0ull)) {
+        if (!done) {
             if (fin >= 0) {
-                finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
+                finish_ray<SCENE>(L, r, c, w, steps, fin, c, fin_surf, ntests);
                 fin = -1;
             }
             if (next == end) {
@@ -619,6 +746,10 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                     safe = face_distance(G, c);
                     steps = 0;
                     active = true;
+                    if (SCENE == 3) {
+                        const uint32_t *tt = tri_tests_of(L, r);
+                        ntests = tt ? tt[r.out] : 0u;   // the straight part before the volume
+                    }
                     if (SCENE == 2) {
 #pragma unroll
                         for (int j = 0; j < kMaxInner; ++j)
@@ -636,109 +767,146 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
                 }
             }
         }
-        // The refilled lanes step in the same iteration: the loop has one
-        // back-edge.
         if (done && __ballot(active) == 0ull) {
-            if (fin >= 0) finish_ray<SCENE != 0>(L, r, c, w, steps, fin, c, fin_surf);
+            if (fin >= 0) finish_ray<SCENE>(L, r, c, w, steps, fin, c, fin_surf, ntests);
             break;
         }
-        if (!active) continue;
-
-        // ---- one step of Eq. 16 with the step of Eq. 18 ----
-        int status = -1;
-        int hit_surf = -1;
-        float te = INFINITY;
-        bool near = safe <= S.near_cap;
-        if (near) {
-            safe = face_distance(G, c);
-            near = safe <= S.near_cap;
-            if (near) {
-                te = exit_distance(G, c, w);
-                if (te <= S.tau) status = 0;
-            }
-        }
-        if (status < 0) {
-            const float4 s = sample_field<DT>(G, field, c);
-            const float n = 1.0f + s.x;
-            const float rn = __builtin_amdgcn_rcpf(n);
-            const float wg = w[0] * s.y + w[1] * s.z + w[2] * s.w;
-            const float pg0 = s.y - wg * w[0], pg1 = s.z - wg * w[1], pg2 = s.w - wg * w[2];
-            float ds;
-            if (S.uniform) {
-                ds = S.ds_uniform;
-            } else {
-                const float pgn = __builtin_amdgcn_sqrtf(pg0 * pg0 + pg1 * pg1 + pg2 * pg2);
-                // clamp to [ds_min, ds_max] (ds_min <= ds_max, checked on the host) in
-                // one med3: fminf/fmaxf would also canonicalize both bounds every step
-                ds = __builtin_amdgcn_fmed3f(n * S.theta_max * __builtin_amdgcn_rcpf(pgn + S.eps), S.ds_min,
-                                             S.ds_max);
-            }
-            ds = te < ds ? te : ds;   // min(ds, te) as a select: fminf would canonicalize both
-            // omega_{k+1} = normalize(omega_k + ds/n P g) = normalize(p + |p| ds/n P g)
-            const float a = ds * rn * pnorm;
-            dw[0] = fmaf(a, pg0, dw[0]);
-            dw[1] = fmaf(a, pg1, dw[1]);
-            dw[2] = fmaf(a, pg2, dw[2]);
-            const float p0 = wr[0] + dw[0], p1 = wr[1] + dw[1], p2 = wr[2] + dw[2];
-            const float pn2 = p0 * p0 + p1 * p1 + p2 * p2;
-            const float inv = __builtin_amdgcn_rsqf(pn2);
-            pnorm = pn2 * inv;
-            w[0] = p0 * inv;
-            w[1] = p1 * inv;
-            w[2] = p2 * inv;
+        // once nothing is left to hand out, step until every lane is done
+        const uint32_t want_idle = done ? 64u : refill_min;
+        for (;;) {
+            if (active) {
+                // ---- one step of Eq. 16 with the step of Eq. 18 ----
+                int status = -1;
+                int hit_surf = -1;
+                float te = INFINITY;
+                bool near = safe <= S.near_cap;
+                if (near) {
+                    safe = face_distance(G, c);
+                    near = safe <= S.near_cap;
+                    if (near) {
+                        te = exit_distance(G, c, w);
+                        if (te <= S.tau) status = 0;
+                    }
+                }
+                if (status < 0) {
+                    const float4 s = sample_field<DT>(G, field, c);
+                    const float n = 1.0f + s.x;
+                    const float rn = __builtin_amdgcn_rcpf(n);
+                    const float wg = w[0] * s.y + w[1] * s.z + w[2] * s.w;
+                    const float pg0 = s.y - wg * w[0], pg1 = s.z - wg * w[1], pg2 = s.w - wg * w[2];
+                    float ds;
+                    if (S.uniform) {
+                        ds = S.ds_uniform;
+                    } else {
+                        const float pgn = __builtin_amdgcn_sqrtf(pg0 * pg0 + pg1 * pg1 + pg2 * pg2);
+                        // clamp to [ds_min, ds_max] (ds_min <= ds_max, checked on the host) in
+                        // one med3: fminf/fmaxf would also canonicalize both bounds every step
+                        ds = __builtin_amdgcn_fmed3f(n * S.theta_max * __builtin_amdgcn_rcpf(pgn + S.eps), S.ds_min,
+                                                     S.ds_max);
+                    }
+                    ds = te < ds ? te : ds;   // min(ds, te) as a select: fminf would canonicalize both
+                    // omega_{k+1} = normalize(omega_k + ds/n P g) = normalize(p + |p| ds/n P g)
+                    const float a = ds * rn * pnorm;
+                    dw[0] = fmaf(a, pg0, dw[0]);
+                    dw[1] = fmaf(a, pg1, dw[1]);
+                    dw[2] = fmaf(a, pg2, dw[2]);
+                    const float p0 = wr[0] + dw[0], p1 = wr[1] + dw[1], p2 = wr[2] + dw[2];
+                    const float pn2 = p0 * p0 + p1 * p1 + p2 * p2;
+                    const float inv = __builtin_amdgcn_rsqf(pn2);
+                    pnorm = pn2 * inv;
+                    w[0] = p0 * inv;
+                    w[1] = p1 * inv;
+                    w[2] = p2 * inv;
+                    float cp[3];   // C_k (SCENE 3)
+                    if (SCENE == 3) {
+                        cp[0] = c[0]; cp[1] = c[1]; cp[2] = c[2];
+                    }
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                // compensated C += ds * w
-                const float y = fmaf(ds, w[k], -cc[k]);
-                const float t = c[k] + y;
-                cc[k] = (t - c[k]) - y;
-                c[k] = t;
-            }
-            ++steps;
-            safe -= ds;
-            int surf = -1;
-            float hp[3];
-            if (SCENE == 2) {
-                // chord C_k -> C_{k+1} = C_{k+1} - ds w: the board whose side value
-                // changes sign (or reaches zero) first along it; ties go to the
-                // lower board index
-                float best = 2.0f;
+                    for (int k = 0; k < 3; ++k) {
+                        // compensated C += ds * w
+                        const float y = fmaf(ds, w[k], -cc[k]);
+                        const float t = c[k] + y;
+                        cc[k] = (t - c[k]) - y;
+                        c[k] = t;
+                    }
+                    ++steps;
+                    safe -= ds;
+                    int surf = -1;
+                    float hp[3];
+                    if (SCENE == 3) {
+                        // chord C_k -> C_{k+1} against the triangles that the shell
+                        // cell of C_k lists, unless the cell's distance bound
+                        // exceeds the step (then no triangle is within reach)
+                        const MeshLaunch &M = L.mesh;
+                        float bl = 2.0f;
+                        if (M.brute) {
+                            for (int k = 0; k < M.ntris; ++k) chord_tri(M, k, cp, c, w, ds, surf, bl, hp);
+                            ntests += (uint32_t)M.ntris;
+                        } else {
+                            int ci[3];
+                            bool in = true;
 #pragma unroll
-                for (int j = 0; j < kMaxInner; ++j) {
-                    if (j >= L.ninner) continue;
-                    const int k = (int)((L.inner_idx >> (8 * j)) & 255u);
-                    const float s0 = side[j], s1 = quad_side(L.quads[k], c);
-                    side[j] = s1;
-                    if (s0 == 0.0f || (s0 > 0.0f && s1 > 0.0f) || (s0 < 0.0f && s1 < 0.0f)) continue;
-                    const float lam = s0 / (s0 - s1);
-                    if (!(lam < best)) continue;
-                    const float back = (1.0f - lam) * ds;
-                    const float h[3] = {fmaf(-back, w[0], c[0]), fmaf(-back, w[1], c[1]), fmaf(-back, w[2], c[2])};
-                    if (!in_quad(L.quads[k], h)) continue;
-                    best = lam;
-                    surf = k;
-                    hp[0] = h[0]; hp[1] = h[1]; hp[2] = h[2];
+                            for (int a = 0; a < 3; ++a) {
+                                ci[a] = (int)floorf((cp[a] - M.lo[a]) * M.inv_cell);
+                                in = in && ci[a] >= 0 && ci[a] < M.res[a];
+                            }
+                            if (in) {
+                                const uint32_t cell = ((uint32_t)ci[2] * (uint32_t)M.res[1] + (uint32_t)ci[1]) *
+                                                          (uint32_t)M.res[0] + (uint32_t)ci[0];
+                                if (M.dlow[cell] <= ds * 1.001f) {
+                                    const uint32_t e0 = M.start[cell], e1 = M.start[cell + 1];
+                                    for (uint32_t e = e0; e < e1; ++e)
+                                        chord_tri(M, (int)M.list[e], cp, c, w, ds, surf, bl, hp);
+                                    ntests += e1 - e0;
+                                }
+                            }
+                        }
+                    }
+                    if (SCENE == 2) {
+                        // chord C_k -> C_{k+1} = C_{k+1} - ds w: the board whose side value
+                        // changes sign (or reaches zero) first along it; ties go to the
+                        // lower board index
+                        float best = 2.0f;
+#pragma unroll
+                        for (int j = 0; j < kMaxInner; ++j) {
+                            if (j >= L.ninner) continue;
+                            const int k = (int)((L.inner_idx >> (8 * j)) & 255u);
+                            const float s0 = side[j], s1 = quad_side(L.quads[k], c);
+                            side[j] = s1;
+                            if (s0 == 0.0f || (s0 > 0.0f && s1 > 0.0f) || (s0 < 0.0f && s1 < 0.0f)) continue;
+                            const float lam = s0 / (s0 - s1);
+                            if (!(lam < best)) continue;
+                            const float back = (1.0f - lam) * ds;
+                            const float h[3] = {fmaf(-back, w[0], c[0]), fmaf(-back, w[1], c[1]),
+                                                fmaf(-back, w[2], c[2])};
+                            if (!in_quad(L.quads[k], h)) continue;
+                            best = lam;
+                            surf = k;
+                            hp[0] = h[0]; hp[1] = h[1]; hp[2] = h[2];
+                        }
+                    }
+                    // a non-finite sample makes n or the direction vector p non-finite
+                    // (or p zero); otherwise the step, direction and position stay finite
+                    if (!(pn2 > 0.0f && pn2 < INFINITY && fabsf(n) < INFINITY))
+                        status = 3;
+                    else if ((SCENE == 2 || SCENE == 3) && surf >= 0) {
+                        c[0] = hp[0]; c[1] = hp[1]; c[2] = hp[2];
+                        status = 0;
+                        hit_surf = surf;
+                    } else if (safe <= S.pos_eps &&
+                               (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] ||
+                                c[2] < G.lo[2] || c[2] > G.hi[2]))
+                        status = 0;
+                    else if ((int32_t)steps >= S.max_steps)
+                        status = 1;
+                }
+                if (status >= 0) {
+                    fin = status;
+                    fin_surf = hit_surf;
+                    active = false;
                 }
             }
-            // a non-finite sample makes n or the direction vector p non-finite
-            // (or p zero); otherwise the step, direction and position stay finite
-            if (!(pn2 > 0.0f && pn2 < INFINITY && fabsf(n) < INFINITY))
-                status = 3;
-            else if (SCENE == 2 && surf >= 0) {
-                c[0] = hp[0]; c[1] = hp[1]; c[2] = hp[2];
-                status = 0;
-                hit_surf = surf;
-            } else if (safe <= S.pos_eps &&
-                     (c[0] < G.lo[0] || c[0] > G.hi[0] || c[1] < G.lo[1] || c[1] > G.hi[1] || c[2] < G.lo[2] ||
-                      c[2] > G.hi[2]))
-                status = 0;
-            else if ((int32_t)steps >= S.max_steps)
-                status = 1;
-        }
-        if (status >= 0) {
-            fin = status;
-            fin_surf = hit_surf;
-            active = false;
+            if ((uint32_t)__popcll(__ballot(!active)) >= want_idle) break;
         }
     }
 }
@@ -758,11 +926,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     march<DT, 2>(L);
 }
 
+template <int DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_march_mesh(TraceLaunch L)
+{
+    march<DT, 3>(L);
+}
+
 template <int DT, int SCENE>
 static constexpr auto march_kernel()
 {
     if constexpr (SCENE == 2)
         return &k_march_boards<DT>;
+    else if constexpr (SCENE == 3)
+        return &k_march_mesh<DT>;
     else
         return &k_march<DT, SCENE>;
 }
@@ -780,7 +956,13 @@ hipError_t launch_raygen(const TraceLaunch &L, bool clear_counters, hipStream_t 
     if (clear_counters)
         hipExtLaunchKernelGGL(k_trace_init, dim3(1), dim3(64), 0, s, t.start, nullptr, 0, L.counters);
     const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
-    hipExtLaunchKernelGGL(k_raygen, g, dim3(kRaygenBlock), 0, s, clear_counters ? nullptr : t.start, nullptr, 0, L);
+    hipEvent_t e0 = clear_counters ? nullptr : t.start;
+    if (L.mesh.ntris > 0)
+        hipExtLaunchKernelGGL(k_raygen<3>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
+    else if (L.nquads > 0)
+        hipExtLaunchKernelGGL(k_raygen<1>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
+    else
+        hipExtLaunchKernelGGL(k_raygen<0>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
     hipExtLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, nullptr, t.stop, 0, L);
     return hipGetLastError();
 }
@@ -801,7 +983,9 @@ static void launch_march_t(int dtype, const TraceLaunch &L, int march_blocks, hi
 
 hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipStream_t s, const KTimer &t)
 {
-    if (L.ninner > 0)
+    if (L.mesh.ntris > 0)
+        launch_march_t<3>(dtype, L, march_blocks, s, t);
+    else if (L.ninner > 0)
         launch_march_t<2>(dtype, L, march_blocks, s, t);
     else if (L.nquads > 0)
         launch_march_t<1>(dtype, L, march_blocks, s, t);
@@ -810,7 +994,7 @@ hipError_t launch_march(int dtype, const TraceLaunch &L, int march_blocks, hipSt
     return hipGetLastError();
 }
 
-int march_scene_mode(const TraceLaunch &L) { return L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0; }
+int march_scene_mode(const TraceLaunch &L) { return L.mesh.ntris > 0 ? 3 : L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0; }
 
 template <int SCENE>
 static hipError_t occupancy(int dtype, int *nb)
@@ -825,7 +1009,8 @@ static hipError_t occupancy(int dtype, int *nb)
 int march_blocks_per_cu(int dtype, int scene_mode)
 {
     int nb = 0;
-    const hipError_t e = scene_mode == 2   ? occupancy<2>(dtype, &nb)
+    const hipError_t e = scene_mode == 3   ? occupancy<3>(dtype, &nb)
+                         : scene_mode == 2 ? occupancy<2>(dtype, &nb)
                          : scene_mode == 1 ? occupancy<1>(dtype, &nb)
                                            : occupancy<0>(dtype, &nb);
     if (e != hipSuccess || nb < 1) nb = 1;

@@ -77,8 +77,8 @@ EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", 
            "hz_profile_select", "hz_profile_read", "hz_membench", "hz_membench_gather", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_trace_scene",
-           "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_release",
-           "hz_server_stop"]
+           "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_timing",
+           "hz_request_release", "hz_server_stop"]
 
 _lib = None
 
@@ -98,8 +98,8 @@ def lib():
         L.hz_ctx_tune.argtypes, L.hz_ctx_tune.restype = [P, C.c_char_p, C.c_int64], S
         L.hz_membench.argtypes = [P, C.c_uint64, C.c_int32, C.POINTER(C.c_double), P]
         L.hz_membench.restype = S
-        L.hz_membench_gather.argtypes = [P, C.POINTER(C.c_int32), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                         C.POINTER(C.c_double), P]
+        L.hz_membench_gather.argtypes = [P, C.POINTER(hz_grid), C.c_int32, C.POINTER(hz_view), C.c_int32, C.c_float,
+                                         C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64), P]
         L.hz_membench_gather.restype = S
         L.hz_profile_enable.argtypes, L.hz_profile_enable.restype = [P, C.c_int32], S
         L.hz_profile_select.argtypes, L.hz_profile_select.restype = [P, C.c_char_p], S
@@ -128,6 +128,8 @@ def lib():
         L.hz_poll.argtypes, L.hz_poll.restype = [P, C.c_uint64, C.POINTER(C.c_double)], S
         L.hz_request_outputs.argtypes = [P, C.c_uint64, C.POINTER(hz_trace_out), C.POINTER(C.c_int64)]
         L.hz_request_outputs.restype = S
+        L.hz_request_timing.argtypes = [P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.hz_request_timing.restype = S
         L.hz_request_release.argtypes, L.hz_request_release.restype = [P, C.c_uint64], S
         L.hz_server_stop.argtypes, L.hz_server_stop.restype = [P], S
         _lib = L
@@ -263,13 +265,17 @@ class Context:
                "membench")
         return g.value
 
-    def membench_gather(self, res, voxel_bytes: int, walkers: int, steps: int, reps: int = 10, stream=None) -> float:
-        """Achievable GB/s of the marcher's 8-corner gathers along straight rays (see hz_membench_gather)."""
-        r = (C.c_int32 * 3)(*[int(v) for v in res])
+    def membench_gather(self, grid, voxel_bytes: int, views: Sequence, step_len: float, reps: int = 10,
+                        stream=None) -> tuple:
+        """Achievable GB/s of the marcher's 8-corner gathers along the views' own
+        rays walked straight through the grid (see hz_membench_gather), and the
+        samples per launch."""
         g = C.c_double()
-        _check(lib().hz_membench_gather(C.c_void_p(self.handle), r, int(voxel_bytes), int(walkers), int(steps),
-                                        int(reps), C.byref(g), _stream(stream)), "membench_gather")
-        return g.value
+        n = C.c_int64()
+        _check(lib().hz_membench_gather(C.c_void_p(self.handle), C.byref(make_grid(grid)), int(voxel_bytes),
+                                        make_views(views), len(views), float(step_len), int(reps), C.byref(g),
+                                        C.byref(n), _stream(stream)), "membench_gather")
+        return g.value, n.value
 
     def profile_enable(self, enable: bool = True):
         _check(lib().hz_profile_enable(C.c_void_p(self.handle), 1 if enable else 0), "profile_enable")
@@ -376,12 +382,21 @@ class Context:
 
     def request_outputs(self, ticket: int, copy: bool = True) -> dict:
         """A completed request's outputs as torch tensors on the GPU (copies by
-        default; with copy=False, views valid until request_release)."""
+        default, complete on return; with copy=False, views valid until
+        request_release, whose reads must have completed before it)."""
         o = hz_trace_out()
         n = C.c_int64()
         _check(lib().hz_request_outputs(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(o), C.byref(n)),
                "request_outputs")
         return _wrap_device_outputs(o, n.value, copy)
+
+    def request_timing(self, ticket: int) -> tuple:
+        """(device start ms, device end ms) of the launch that carried a
+        completed request, from the server's start."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib().hz_request_timing(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(a), C.byref(b)),
+               "request_timing")
+        return a.value, b.value
 
     def request_release(self, ticket: int):
         _check(lib().hz_request_release(C.c_void_p(self.handle), C.c_uint64(ticket)), "request_release")
@@ -415,4 +430,7 @@ def _wrap_device_outputs(o: hz_trace_out, n: int, copy: bool = True) -> dict:
     for name, ptr, shape, ts in spec:
         t = torch.as_tensor(_DeviceArray(ptr, shape, ts), device="cuda")
         out[name] = t.clone() if copy else t
+    if copy:
+        # the library reuses the memory once the request is released
+        torch.cuda.current_stream().synchronize()
     return out

@@ -62,40 +62,68 @@ def assert_field_match(gpu_dn, gpu_g, ref_dn, ref_g, spacing, label: str = "", r
     assert e_dn <= rel * scale, msg
 
 
-def oracle_sensitivity(oracle, grid, dn, views, step, ray_ids=None, trials: int = 3, rel: float = 3e-7,
-                       seed: int = 0) -> dict:
-    """Per-ray spread of the FP64 oracle's own answer when its delta-n grid is
-    perturbed by relative noise of the size of the FP32 splat's error.  Rays in
-    strongly focusing regions (caustics, grazing exits through the steep band
-    at the box faces) can move by more than the fixed tolerances under such
-    perturbations; no FP32 implementation can be held closer than that."""
-    base = oracle.trace_views(oracle.Medium.from_grid(grid, dn), views, step, ray_ids=ray_ids)
+def oracle_sensitivity(oracle, grid, dn, views, step, ray_ids=None, trials: int = 4, rel: float = 5e-7,
+                       step_rel: float = 5e-7, pos_ulps: float = 1.0, seed: int = 0) -> dict:
+    """Per-ray spread of the FP64 oracle's own answer under perturbations of
+    the size of the FP32 path's rounding, the largest over all trials:
+      * the delta-n grid times (1 + rel N(0,1)) per voxel, `trials` draws (the
+        GPU field differs from the oracle's by 4e-7 to 1.2e-6 of max |delta-n|);
+      * the whole field (grid box included) shifted by -/+ pos_ulps units in
+        the last place of the largest cell coordinate, along each axis in turn:
+        the tracer holds the cell coordinate u = x / spacing - 1/2 in FP32, so
+        every sample and face test carries that much position rounding;
+      * with the adaptive rule, theta_max times (1 -/+ step_rel): the FP32 step
+        length carries a few ulps of rounding.
+    Rays in strongly focusing regions (caustics, grazing exits through the
+    steep band at the box faces) move by more than the fixed tolerances under
+    such perturbations: no FP32 implementation can be held closer than that."""
+    import dataclasses
+    from paper_2603_02048_amd import workloads as W
+    base_md = oracle.Medium.from_grid(grid, dn)
+    base = oracle.trace_views(base_md, views, step, ray_ids=ray_ids)
     rng = np.random.default_rng(seed)
     s = dict(pos=0.0, dir=0.0, px=0.0)
-    for _ in range(trials):
-        md = oracle.Medium.from_grid(grid, dn * (1.0 + rel * rng.standard_normal(dn.shape)))
-        r = oracle.trace_views(md, views, step, ray_ids=ray_ids)
+    runs = [(oracle.Medium.from_grid(grid, dn * (1.0 + rel * rng.standard_normal(dn.shape))), step)
+            for _ in range(trials)]
+    d = pos_ulps * float(np.max(grid.res)) * 2.0 ** -23
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            off = np.zeros(3)
+            off[axis] = sgn * d * grid.spacing[axis]
+            runs.append((oracle.Medium.from_grid(W.make_grid(grid.lo + off, grid.hi + off, grid.res), dn), step))
+    if not step.uniform:
+        runs += [(base_md, dataclasses.replace(step, theta_max=step.theta_max * (1.0 + f * step_rel)))
+                 for f in (-1.0, 1.0)]
+    for md, st in runs:
+        r = oracle.trace_views(md, views, st, ray_ids=ray_ids)
         s["pos"] = np.maximum(s["pos"], np.linalg.norm(r["exit_pos"] - base["exit_pos"], axis=1) / grid.voxel)
         s["dir"] = np.maximum(s["dir"], np.linalg.norm(r["exit_dir"] - base["exit_dir"], axis=1))
-        d = np.abs(r["disp"] - base["disp"]).max(axis=1)
-        s["px"] = np.maximum(s["px"], np.where(np.isnan(d), 0.0, d))
+        dd = np.abs(r["disp"] - base["disp"]).max(axis=1)
+        s["px"] = np.maximum(s["px"], np.where(np.isnan(dd), 0.0, dd))
     return s
 
 
 def assert_rays_match_conditioned(gpu: dict, ref: dict, sens: dict, voxel: float, label: str = "",
-                                  strict_fraction: float = 0.995, loose: float = 10.0):
-    """Stress fields: at least `strict_fraction` of the rays within the plain
-    tolerances and every ray within `loose` times them.  The oracle's own
-    spread under FP32-sized perturbations of its field (`sens`) is reported:
-    on these fields it reaches the plain tolerance for a few rays."""
+                                  factor: float = 3.0, strict_fraction: float = 0.995):
+    """Stress fields, per ray: every error within `factor` times the larger of
+    the plain tolerance and that ray's own measured oracle spread (`sens`,
+    from oracle_sensitivity), for exit position, direction and displacement
+    alike; statuses equal and steps within one; and at least
+    `strict_fraction` of the rays within the plain tolerances."""
     err = ray_errors(gpu, ref, voxel)
+    tol = dict(pos=TOL_POS_VOX, dir=TOL_DIR, px=TOL_PX)
     strict = (err["pos"] <= TOL_POS_VOX) & (err["dir"] <= TOL_DIR) & (err["px"] <= TOL_PX)
-    ok = ((err["pos"] <= loose * TOL_POS_VOX) & (err["dir"] <= loose * TOL_DIR) & (err["px"] <= loose * TOL_PX))
-    msg = (f"{label}: {summary(err)}; strict {strict.mean() * 100:.3f}% of rays, "
-           f"within {loose:g}x {ok.mean() * 100:.3f}%, worst oracle self-sensitivity {np.max(sens['dir']):.2e} rad")
+    ratio = np.zeros_like(err["pos"])
+    for k in tol:
+        ratio = np.maximum(ratio, err[k] / np.maximum(tol[k], sens[k]))
+    worst = int(np.argmax(ratio))
+    msg = (f"{label}: {summary(err)}; strict {strict.mean() * 100:.3f}% of rays; worst error / max(tol, own spread) "
+           f"{ratio[worst]:.2f} (ray {worst}: pos {err['pos'][worst]:.2e} vs spread {sens['pos'][worst]:.2e}, dir "
+           f"{err['dir'][worst]:.2e} vs {sens['dir'][worst]:.2e}, px {err['px'][worst]:.2e} vs {sens['px'][worst]:.2e}); "
+           f"{int((~strict).sum())} rays outside the plain tolerances")
     print(msg, flush=True)
     assert err["status_equal"], msg
     assert err["steps_diff"].max() <= 1, msg
-    assert ok.all(), msg
+    assert ratio.max() <= factor, msg
     assert strict.mean() >= strict_fraction, msg
     return err

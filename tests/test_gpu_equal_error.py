@@ -1,7 +1,7 @@
 """Adaptive vs uniform step at equal displacement-map error (Sec. 3.3.3, Eq. 18;
-the theta_max accuracy/speed trade-off of Sec. 4.1).
+the theta_max accuracy/speed trade-off of Sec. 4.1), through the protocol the
+benchmark reports (bench.equal_error_protocol):
 
-Protocol:
   1. E_u = RMS (and max) |disp_GPU,uniform(0.25 voxel) - disp_ref| on a
      4,096-ray subset, where disp_ref is the oracle's converged solution of the
      continuous ray equation through the same FP64 field (step halving +
@@ -15,15 +15,12 @@ the adaptive rule binds at the paper's theta.  The numbers are printed as one
 JSON line per field.
 """
 import json
-import math
 
-import numpy as np
 import pytest
-import torch
 
+import bench
 import oracle
 from paper_2603_02048_amd import workloads as W
-from tests.parity import to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -35,28 +32,6 @@ def haze():
     return h
 
 
-def _rms_max(disp, ref):
-    e = np.linalg.norm(disp.astype(np.float64) - ref, axis=1)
-    e = e[np.isfinite(e)]
-    return float(np.sqrt(np.mean(e ** 2))), float(np.max(e))
-
-
-def _time_trace(ctx, field, views, st, reps=5):
-    out = ctx.trace_views(field, views, st)
-    torch.cuda.synchronize()
-    ctx.profile_read("march", reset=True)
-    ctx.profile_enable(True)
-    for _ in range(reps):
-        ctx.trace_views(field, views, st, out=out)
-    torch.cuda.synchronize()
-    ctx.profile_enable(False)
-    ms = (ctx.profile_read("raygen")[0] + ctx.profile_read("march")[0]) / reps
-    ctx.profile_read("march", reset=True)
-    steps = int(out["steps"].sum().item())
-    nrays = sum(v.nrays for v in views)
-    return dict(ms=ms, rays_per_s=nrays / (ms * 1e-3), ray_steps_per_s=steps / (ms * 1e-3), ray_steps=steps)
-
-
 @pytest.mark.parametrize("kgd", [1.0, 250.0])
 def test_equal_error_protocol(haze, kgd):
     wl = W.make_config(2).with_k_gd(kgd)
@@ -65,59 +40,15 @@ def test_equal_error_protocol(haze, kgd):
     try:
         field = ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
         md = oracle.field(wl.particles, wl.grid, wl.k_gd, wl.h)
-        ids_np = wl.subset
-        # converged to 2e-5 px between successive halvings (then Richardson), well
-        # below the errors compared here
-        ref = oracle.reference_views(md, wl.views, wl.step_uniform, ray_ids=ids_np, max_levels=10,
-                                     tol_px=2e-5, tol_dir=1e-7)
-        ids = torch.from_numpy(ids_np).cuda()
-        uni = to_np(ctx.trace_views(field, wl.views, wl.step_uniform, ray_ids=ids))
-        e_u = _rms_max(uni["disp"], ref["disp"])
-
-        def err_at(theta):
-            st, _ = W.make_steps(wl.grid, theta_max=theta)
-            out = to_np(ctx.trace_views(field, wl.views, st, ray_ids=ids))
-            return _rms_max(out["disp"], ref["disp"]), int(out["steps"].sum())
-
-        sweep = {}
-        theta = 0.003
-        while theta > 1e-9:
-            sweep[theta] = err_at(theta)
-            if sweep[theta][0][0] <= e_u[0]:
-                break
-            theta /= 3.0
-        assert sweep[theta][0][0] <= e_u[0], "no theta in the sweep reached the uniform step's error"
-        lo_t = theta
-        hi_t = theta * 3.0 if theta < 0.003 else theta
-        for _ in range(6):   # bisect in log(theta): largest theta with E_a <= E_u
-            if hi_t <= lo_t:
-                break
-            mid = math.sqrt(lo_t * hi_t)
-            e = err_at(mid)
-            sweep[mid] = e
-            if e[0][0] <= e_u[0]:
-                lo_t = mid
-            else:
-                hi_t = mid
-        theta_eq = lo_t
-        st_eq, _ = W.make_steps(wl.grid, theta_max=theta_eq)
-        t_a = _time_trace(ctx, field, wl.views, st_eq)
-        t_p = _time_trace(ctx, field, wl.views, wl.step_adaptive)
-        t_u = _time_trace(ctx, field, wl.views, wl.step_uniform)
-        summary = {
-            "field": f"config2 kgd x{kgd:g}", "subset_rays": int(ids_np.size),
-            "reference_converged_fraction": float(np.mean(ref["converged"])),
-            "E_uniform_px": {"rms": e_u[0], "max": e_u[1]},
-            "theta_eq": theta_eq, "E_adaptive_at_theta_eq_px": {"rms": sweep[theta_eq][0][0],
-                                                                "max": sweep[theta_eq][0][1]},
-            "E_adaptive_at_paper_theta_px": {"rms": sweep[0.003][0][0], "max": sweep[0.003][0][1]},
-            "uniform": t_u, "adaptive_at_theta_eq": t_a, "adaptive_at_paper_theta": t_p,
-            "speedup_at_equal_error": t_u["ms"] / t_a["ms"],
-            "sweep": {f"{k:.3g}": {"rms_px": v[0][0], "max_px": v[0][1], "subset_steps": v[1]}
-                      for k, v in sorted(sweep.items(), reverse=True)},
-        }
-        print("EQUAL_ERROR " + json.dumps(summary), flush=True)
-        assert summary["E_adaptive_at_theta_eq_px"]["rms"] <= e_u[0]
+        res = bench.equal_error_protocol(oracle, ctx, field, md, wl)
+        assert "error" not in res, res
+        res["field"] = f"config2 kgd x{kgd:g}"
+        print("EQUAL_ERROR " + json.dumps(res), flush=True)
+        # the physical field's reference converges everywhere; on the stress
+        # field some rays pass near caustics (reported, not asserted)
+        if kgd == 1.0:
+            assert res["reference_converged_fraction"] > 0.99
+        assert res["E_adaptive_px"]["rms"] <= res["E_uniform_px"]["rms"]
         field.release()
     finally:
         ctx.close()

@@ -137,3 +137,46 @@ def test_serve_budget_admission_and_errors(haze):
         ctx.server_stop()
     finally:
         ctx.close()
+
+
+def test_serve_slots_overlap_on_device(haze):
+    """Batches on two slots run at the same time on the device: requests for
+    fields of different grids cannot share a launch, so each pair goes to two
+    slots, and the dispatch timestamps of the two launches overlap."""
+    print("case serve overlap: 3 pairs of 64x32 requests, two grids, 1/64-voxel uniform steps", flush=True)
+    ctx = haze.Context(0)
+    try:
+        a = W.make_small(seed=21, n=4000, res=(48, 40, 32), width=8, height=8, nviews=1)
+        b = W.make_small(seed=22, n=4000, res=(40, 48, 32), width=8, height=8, nviews=1)
+        fa = ctx.splat_index_field(haze.upload_particles(a.particles), a.grid, a.k_gd, a.h)
+        fb = ctx.splat_index_field(haze.upload_particles(b.particles), b.grid, b.k_gd, b.h)
+        torch.cuda.synchronize()
+        # few rays (8 march workgroups each), many steps: each launch occupies
+        # a few CUs for about a millisecond
+        _, st_a = W.make_steps(a.grid, uniform_vox=1.0 / 64.0)
+        _, st_b = W.make_steps(b.grid, uniform_vox=1.0 / 64.0)
+        va = [W.ring_view(a.grid.lo, a.grid.hi, 0.4, 1.2, 64, 32)]
+        vb = [W.ring_view(b.grid.lo, b.grid.hi, 1.1, 1.2, 64, 32)]
+        ctx.server_start(slots=2, max_batch_rays=1 << 16)
+        overlaps = []
+        for rep in range(3):
+            ta = ctx.submit(fa, va, st_a)
+            tb = ctx.submit(fb, vb, st_b)
+            _wait(ctx, [ta, tb])
+            (s0, e0), (s1, e1) = ctx.request_timing(ta), ctx.request_timing(tb)
+            assert e0 > s0 and e1 > s1
+            ov = min(e0, e1) - max(s0, s1)
+            overlaps.append(ov / min(e0 - s0, e1 - s1))
+            print(f"pair {rep}: A [{s0:.3f}, {e0:.3f}] ms, B [{s1:.3f}, {e1:.3f}] ms, overlap {overlaps[-1]:.2f} "
+                  f"of the shorter", flush=True)
+            got = to_np(ctx.request_outputs(ta))
+            solo = to_np(ctx.trace_views(fa, va, st_a))
+            torch.cuda.synchronize()
+            for k in solo:
+                assert np.array_equal(got[k].view(np.uint8), solo[k].view(np.uint8)), k
+            ctx.request_release(ta)
+            ctx.request_release(tb)
+        assert min(overlaps) > 0.2, overlaps
+        ctx.server_stop()
+    finally:
+        ctx.close()
