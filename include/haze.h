@@ -270,6 +270,24 @@ hz_status hz_trace_views(hz_ctx *ctx, const hz_field *field, const hz_view *view
                          const hz_step *step, const int64_t *ray_ids, int64_t nrays, const hz_trace_out *out,
                          void *hip_stream);
 
+/* hz_trace_views for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results (bitwise equal to hz_trace_views), but the
+ * launch scratch (ray counters, view table, hit list, length bins) lives in
+ * one static device array of the library, about 40 MiB, that each GPU the
+ * library runs on holds until the process ends.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine; the view table
+ * reaches the device in kernel arguments).  Limits: at most 64 views and
+ * 2^23 queue slots (each view is padded to 8 x 8 pixel tiles; with ray_ids,
+ * nrays slots); beyond them it returns HZ_E_UNSUPPORTED without doing
+ * anything.  Every call on one GPU shares that GPU's array, and the array
+ * keeps the last call's contents: calls that overlap on one GPU (on two
+ * streams, or from two contexts) race and give wrong results, so order them.
+ * Arguments, outputs and other errors as hz_trace_views. */
+hz_status hz_trace_views_noalloc(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                                 const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                                 const hz_trace_out *out, void *hip_stream);
+
 /* Scene boards (paper Sec. 3.3.2: the image is formed where the bent ray meets
  * the scene; Sec. 4.2: boards at two depths, or one slanted board, viewed
  * through the volume).  A board is the parallelogram

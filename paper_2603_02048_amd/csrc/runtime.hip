@@ -40,6 +40,7 @@ hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3]
 hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
 hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
+hipError_t launch_put_table(void *dst, const void *src, size_t bytes, hipStream_t s);
 int march_blocks_per_cu(int, int);
 }  // namespace haze
 
@@ -337,6 +338,8 @@ static void scratch_free(hz_ctx *c, Scratch &s)
     s = Scratch{};
 }
 
+static hz_status noalloc_setup(int device);
+
 extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx **out)
 {
     if (!out) return fail(HZ_E_INVALID, "hz_ctx_create: out is NULL");
@@ -362,6 +365,16 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
         c->march_bpc_scene[1][d] = march_blocks_per_cu(d, 2);
     }
     c->pinned.resize(8);
+    // the completion-mark events exist from the start, so issuing a mark
+    // never creates one (hz_trace_views_noalloc issues marks)
+    for (hipEvent_t &ev : c->marks) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            for (hipEvent_t &x : c->marks)
+                if (x) (void)hipEventDestroy(x);
+            delete c;
+            return fail(HZ_E_DEVICE, "hz_ctx_create: hipEventCreate failed");
+        }
+    }
     void *fw = nullptr, *fwd = nullptr;
     if (hipHostMalloc(&fw, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostGetDevicePointer(&fwd, fw, 0) != hipSuccess) {
@@ -372,6 +385,11 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
     c->fault_word = (uint32_t *)fw;
     c->fault_word_dev = (uint32_t *)fwd;
     *c->fault_word = 0u;
+    const hz_status st = noalloc_setup(device);
+    if (st != HZ_OK) {
+        hz_ctx_destroy(c);
+        return st;
+    }
     *out = c;
     return HZ_OK;
 }
@@ -1327,6 +1345,90 @@ extern "C" hz_status hz_trace_scene(hz_ctx *c, const hz_field *fc, const hz_view
 {
     return trace_impl(c, fc, views, nviews, scene, step, ray_ids, nrays, out, surface, hip_stream,
                       "hz_trace_scene");
+}
+
+// ---------------------------------------------------------------------------
+// tracing without allocation
+// ---------------------------------------------------------------------------
+// hz_trace_views_noalloc runs the kernels of hz_trace_views with their launch
+// scratch (counter sets, view table, hit list, length bins) in one file-scope
+// device array instead of context memory.  Each GPU holds its own copy of the
+// array for the life of the process; host code never uses the array's name as
+// an address: hz_ctx_create looks up the array's address on the context's
+// device once (hipGetSymbolAddress) and every call uses that.
+constexpr int32_t kNoAllocViews = 64;
+constexpr int64_t kNoAllocSlots = (int64_t)1 << 23;
+constexpr size_t kNoAllocTableOff = (kCounterBytes + 255) & ~(size_t)255;
+constexpr size_t kNoAllocHitsOff = (kNoAllocTableOff + kNoAllocViews * sizeof(TraceJob) + 255) & ~(size_t)255;
+constexpr size_t kNoAllocBinsOff = kNoAllocHitsOff + 4 * (size_t)kNoAllocSlots;
+constexpr size_t kNoAllocBytes = kNoAllocBinsOff + (size_t)kNoAllocSlots;
+static_assert(sizeof(TraceJob) % 4 == 0, "the view table is copied in 32-bit words");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kNoAllocMaxDevices] = {};
+
+// Once per device, with that device current: the address of `scratch` there.
+static hz_status noalloc_setup(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return HZ_OK;   // the entry point then reports it
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_addr[device]) return HZ_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(HZ_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[device] = p;
+    return HZ_OK;
+}
+
+static void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch_addr[device];
+}
+
+extern "C" hz_status hz_trace_views_noalloc(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                                            const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                                            const hz_trace_out *out, void *hip_stream)
+{
+    const char *fn = "hz_trace_views_noalloc";
+    TraceJob jobs[kNoAllocViews];
+    TraceLaunch L;
+    hz_status st = prepare_trace(c, fc, views, nviews, kNoAllocViews, step, ray_ids, nrays, out, nullptr, jobs, &L,
+                                 fn);
+    if (st != HZ_OK) return st;
+    if (L.nslots > kNoAllocSlots)
+        return fail(HZ_E_UNSUPPORTED,
+                    "%s: %lld queue slots (views padded to 8x8 pixel tiles, or ray ids) exceed the static scratch "
+                    "of %lld", fn, (long long)L.nslots, (long long)kNoAllocSlots);
+    if (L.nslots == 0) return HZ_OK;
+    unsigned char *base = (unsigned char *)noalloc_scratch(c->device);
+    if (!base) return fail(HZ_E_DEVICE, "%s: no static scratch address for device %d", fn, c->device);
+    hz_field *f = const_cast<hz_field *>(fc);
+    HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    st = field_order_read(c, f, s);
+    if (st != HZ_OK) return st;
+    HZ_HIP(launch_put_table(base + kNoAllocTableOff, jobs, sizeof(TraceJob) * (size_t)nviews, s), "table launch");
+    L.jobs = (const TraceJob *)(base + kNoAllocTableOff);
+    L.hits = (uint32_t *)(base + kNoAllocHitsOff);
+    L.slot_bin = base + kNoAllocBinsOff;
+    // every call clears its counter set (k_trace_init); the other set only
+    // receives ray generation's clearing for a next launch
+    L.counters = (uint32_t *)base;
+    L.counters_next = (uint32_t *)base + kCounterSetWords;
+    const int dt = (int)f->dtype;
+    HZ_HIP(launch_raygen(L, true, s, KTimer{}), "raygen launch");
+    HZ_HIP(launch_march(dt, L, march_grid_blocks(c, L, dt), s, KTimer{}), "march launch");
+    CallMark done;
+    st = mark_issue(c, s, &done);
+    if (st != HZ_OK) return st;
+    field_mark_used(f, done);
+    return HZ_OK;
 }
 
 // ---------------------------------------------------------------------------

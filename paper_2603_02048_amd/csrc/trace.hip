@@ -37,6 +37,9 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+#include <cstring>
+
 namespace haze {
 
 struct Ray {
@@ -370,6 +373,20 @@ __device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, c
     }
     if (st) st[o] = steps;
     if (stat) stat[o] = (uint8_t)status;
+}
+
+// Part of a job table carried in the kernel arguments: the tracer's view
+// table reaches the device without a host staging buffer.
+constexpr int kTableChunkWords = 240;
+struct TableChunk {
+    uint32_t offset;   // destination word offset
+    uint32_t nwords;
+    uint32_t w[kTableChunkWords];
+};
+
+__global__ __launch_bounds__(256) void k_put_table(uint32_t *__restrict__ dst, TableChunk c)
+{
+    for (uint32_t i = threadIdx.x; i < c.nwords; i += blockDim.x) dst[c.offset + i] = c.w[i];
 }
 
 // Zero the bin totals, the placement cursors and the march batch head.
@@ -946,6 +963,21 @@ static constexpr auto march_kernel()
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+
+// Copy `bytes` (a multiple of 4) of host memory to device memory at `dst`
+// through kernel arguments, in chunks of kTableChunkWords words.
+hipError_t launch_put_table(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    TableChunk c;
+    const uint32_t total = (uint32_t)(bytes / 4);
+    for (uint32_t off = 0; off < total; off += kTableChunkWords) {
+        c.offset = off;
+        c.nwords = std::min<uint32_t>(kTableChunkWords, total - off);
+        std::memcpy(c.w, (const uint32_t *)src + off, 4u * c.nwords);
+        hipLaunchKernelGGL(k_put_table, dim3(1), dim3(256), 0, s, (uint32_t *)dst, c);
+    }
+    return hipGetLastError();
+}
 
 // Ray generation for L.nslots > 0 slots; `clear_counters` when the set
 // L.counters was not cleared by the previous launch's ray generation (new

@@ -76,7 +76,7 @@ class hz_scene(C.Structure):
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
            "hz_profile_select", "hz_profile_read", "hz_membench", "hz_membench_gather", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
-           "hz_trace_scene",
+           "hz_trace_views_noalloc", "hz_trace_scene",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_timing",
            "hz_request_release", "hz_server_stop"]
 
@@ -119,6 +119,8 @@ def lib():
         L.hz_trace_views.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), P, C.c_int64,
                                      C.POINTER(hz_trace_out), P]
         L.hz_trace_views.restype = S
+        L.hz_trace_views_noalloc.argtypes = L.hz_trace_views.argtypes
+        L.hz_trace_views_noalloc.restype = S
         L.hz_trace_scene.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_scene), C.POINTER(hz_step),
                                      P, C.c_int64, C.POINTER(hz_trace_out), P, P]
         L.hz_trace_scene.restype = S
@@ -338,6 +340,24 @@ class Context:
             assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
         _check(lib().hz_trace_views(C.c_void_p(self.handle), C.c_void_p(field.handle), vs, len(views),
                                     C.byref(st), _ptr(ray_ids), n, C.byref(o), _stream(stream)), "trace_views")
+        return out
+
+    def trace_views_noalloc(self, field: Field, views: Sequence, step, ray_ids: Optional[torch.Tensor] = None,
+                            out: Optional[dict] = None, stream=None) -> dict:
+        """trace_views with the launch scratch in the library's static device
+        array (hz_trace_views_noalloc): the call allocates no device memory
+        (`out` is allocated here when not given)."""
+        total = sum(int(v.width) * int(v.height) for v in views)
+        n = total if ray_ids is None else int(ray_ids.numel())
+        if out is None:
+            out = alloc_outputs(n)
+        o = hz_trace_out(_ptr(out.get("disp")), _ptr(out.get("exit_pos")), _ptr(out.get("exit_dir")),
+                         _ptr(out.get("steps")), _ptr(out.get("status")))
+        if ray_ids is not None:
+            assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
+        _check(lib().hz_trace_views_noalloc(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
+                                            len(views), C.byref(make_step(step)), _ptr(ray_ids), n, C.byref(o),
+                                            _stream(stream)), "trace_views_noalloc")
         return out
 
     def trace_scene(self, field: Field, views: Sequence, quads, step, ray_ids: Optional[torch.Tensor] = None,
