@@ -330,6 +330,71 @@ hz_status hz_trace_scene(hz_ctx *ctx, const hz_field *field, const hz_view *view
                          const hz_trace_out *out, uint8_t *surface, void *hip_stream);
 
 /* ---------------------------------------------------------------------- */
+/* Triangle-mesh scenes with a conservative shell (paper Sec. 4.1)        */
+/* ---------------------------------------------------------------------- */
+
+/* A scene triangle, seen from either side; `surface` (0..253) names the part
+ * of the scene it belongs to, and a ray that meets it reports surface + 1. */
+typedef struct {
+    float v0[3], v1[3], v2[3];
+    int32_t surface;
+} hz_triangle;
+
+/* reach: the longest march step the shell must serve, in metres: a trace
+ *   whose largest step (ds_max, or ds_uniform for the fixed step) exceeds it
+ *   is refused.
+ * cell: edge of the shell's grid cells in metres; 0 = 4 x reach.  Coarsened
+ *   by factors of 1.25 until the grid has at most 512 cells per axis and
+ *   2^22 cells.
+ * brute_force: 1 = no shell: every chord and straight segment is tested
+ *   against every triangle (same results, for comparison). */
+typedef struct {
+    float reach;
+    float cell;
+    int32_t brute_force;
+} hz_mesh_params;
+
+typedef struct hz_mesh hz_mesh;   /* device-resident triangles and their shell */
+
+/* Build a mesh scene from ntris host triangles (1..65536) and precompute its
+ * conservative shell (paper Sec. 4.1): a coarse grid over the mesh's box
+ * grown by reach + one cell, holding per cell a lower bound of the distance
+ * from any point of the cell to the mesh, and the triangles within reach of
+ * the cell.  During the march, a step starting in a cell whose bound exceeds
+ * the step cannot meet the mesh and takes no exact test; otherwise the
+ * step's chord is tested against the cell's triangles.  Straight parts of the
+ * ray (before the volume, rays that miss it, the exit ray) walk the cells
+ * they cross.  Built on the device in two passes over all triangles per cell
+ * (cost cells x triangles); synchronises hip_stream.
+ * Errors: HZ_E_INVALID (NULL arguments, ntris out of range, non-finite or
+ * degenerate triangles, surface outside [0, 253], reach <= 0, cell < 0),
+ * HZ_E_UNSUPPORTED (lists too long), HZ_E_BUDGET, HZ_E_NOMEM, HZ_E_DEVICE. */
+hz_status hz_mesh_create(hz_ctx *ctx, const hz_triangle *tris, int32_t ntris, const hz_mesh_params *params,
+                         void *hip_stream, hz_mesh **out);
+
+/* Triangles, shell grid size and cell, total length of the shell's lists,
+ * and device bytes of a mesh (any pointer may be NULL). */
+hz_status hz_mesh_info(const hz_mesh *mesh, int32_t *ntris, int32_t shell_res[3], float *shell_cell,
+                       int64_t *list_entries, uint64_t *bytes);
+
+/* Release a mesh; waits for the traces that use it. */
+hz_status hz_mesh_release(hz_ctx *ctx, hz_mesh *mesh);
+
+/* hz_trace_scene with a triangle mesh instead of boards.  The first triangle
+ * met ends the ray: met before the volume (straight ray from the eye), on the
+ * chord C_k -> C_{k+1} of a step of Eq. 16 inside it (first crossing along the
+ * chord; equal crossings go to the lower triangle index), or after it (the
+ * straight exit ray against the mesh and the view's backdrop plane; the mesh
+ * wins ties).  Outputs as hz_trace_scene (surface: 0 backdrop, s + 1 a
+ * triangle of surface s, 255 nothing met), plus, if tri_tests (device, one
+ * uint32 per output) is not NULL, the number of exact ray-triangle tests each
+ * ray took.  Errors: as hz_trace_views, and HZ_E_INVALID for a NULL mesh, a
+ * mesh of another context, or steps longer than the mesh's reach. */
+hz_status hz_trace_mesh(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                        const hz_mesh *mesh, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                        const hz_trace_out *out, uint8_t *surface, uint32_t *tri_tests, void *hip_stream);
+
+/* ---------------------------------------------------------------------- */
 /* Measurement: achievable bandwidth of the memory levels the tracer uses   */
 /* ---------------------------------------------------------------------- */
 

@@ -145,6 +145,8 @@ struct SceneQuad {
 // cannot meet the mesh and takes no exact test; straight rays walk the cells
 // they cross (3D DDA) and test the cells' lists.  brute = 1: no shell, every
 // test against every triangle (for comparison).
+constexpr int32_t kMaxMeshTriangles = 65536;
+constexpr int64_t kMaxShellCells = (int64_t)1 << 22;
 struct MeshLaunch {
     const SceneQuad *tris;
     const uint8_t *surf;       // surface id of each triangle (a hit reports it + 1)

@@ -18,6 +18,8 @@ namespace haze {
 hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
                    const char *fn, int index);
 void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G);
+float length_bin_scale(const hz_grid &g);
+hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 
 // Grid-stride read of n float4; each block writes one partial sum so the
 // loads cannot be optimised away.
@@ -48,49 +50,34 @@ __global__ void k_init(float4 *a, int64_t n)
 typedef uint32_t gb_u32x4 __attribute__((ext_vector_type(4), aligned(8)));
 typedef const gb_u32x4 __attribute__((address_space(1))) *gb_ptr;
 
-// One thread per queue slot of the views, in the tracer's order (8 x 8 pixel
-// tiles, view after view): the thread casts its pixel's pinhole ray and, if
-// it enters the grid box, walks straight through it in steps of `step`
-// metres from the entry point, reading at every sample the 8 corners of its
-// cell as the marcher does (cell index clamped to [0, R-2]; the two
-// x-neighbours of each of the 4 rows in one 16 or 32 byte stretch).  The words
-// are folded into one value per thread so no load can be dropped; the samples
-// are counted (one atomic per wave).
+// One thread per entering ray, in the order of the tracer's length-sorted
+// hit list (the order the march hands rays to its waves: 64 consecutive hits
+// per wave, longest rays first): the thread casts its pixel's pinhole ray
+// and walks straight through the grid box in steps of `step` metres from the
+// entry point, reading at every sample the 8 corners of its cell as the
+// marcher does (cell index clamped to [0, R-2]; the two x-neighbours of each
+// of the 4 rows in one 16 or 32 byte stretch).  The words are folded into
+// one value per thread so no load can be dropped; the samples are counted
+// (one atomic per wave).
 template <int EB>
-__global__ __launch_bounds__(256) void k_gather_views(const char *__restrict__ f, TraceGrid G,
-                                                      const TraceJob *__restrict__ jobs, int32_t njobs,
-                                                      int64_t nslots, float step, uint32_t *__restrict__ sink,
-                                                      unsigned long long *__restrict__ nsamples)
+__global__ __launch_bounds__(256) void k_gather_hits(const char *__restrict__ f, TraceLaunch L, uint32_t nh,
+                                                     float step, uint32_t *__restrict__ sink,
+                                                     unsigned long long *__restrict__ nsamples)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0u, n = 0u;
-    if (slot < nslots) {
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].slot_begin <= slot)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const TraceJob &J = jobs[lo];
-        const int32_t local = (int32_t)(slot - J.slot_begin);
-        const int32_t tile = local >> 6, within = local & 63;
-        const int32_t ty = tile / J.tiles_x;
-        const int32_t p = (tile - ty * J.tiles_x) * 8 + (within & 7), q = ty * 8 + (within >> 3);
+    if (k < nh) {
+        Ray r;
+        decode_slot(L, L.hits[k], r);
+        const TraceJob &J = L.jobs[r.job];
+        const float3 d3 = pixel_dir(J, r.p, r.q);
+        const float d[3] = {d3.x, d3.y, d3.z};
         float t0 = 0.0f, t1 = 0.0f;
-        float d[3] = {0.0f, 0.0f, 0.0f};
-        bool in = false;
-        if (p < J.width && q < J.height) {
-            const float3 d3 = pixel_dir(J, p, q);
-            d[0] = d3.x;
-            d[1] = d3.y;
-            d[2] = d3.z;
-            in = enter_volume(G, J.eye, d, t0, &t1);
-        }
+        const bool in = enter_volume(L.grid, J.eye, d, t0, &t1);
+        const TraceGrid &G = L.grid;
         const uint32_t row = (uint32_t)G.res[0], slab = (uint32_t)G.res[0] * (uint32_t)G.res[1];
-        for (uint32_t k = 0; in; ++k) {
-            const float t = fmaf((float)k, step, t0);
+        for (uint32_t s = 0; in; ++s) {
+            const float t = fmaf((float)s, step, t0);
             if (!(t < t1)) break;
             uint32_t i[3];
 #pragma unroll
@@ -112,7 +99,7 @@ __global__ __launch_bounds__(256) void k_gather_views(const char *__restrict__ f
             }
             ++n;
         }
-        sink[slot] = acc;
+        sink[k] = acc;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) n += (uint32_t)__shfl_xor((int)n, off);
@@ -164,7 +151,6 @@ extern "C" hz_status hz_membench_gather(hz_ctx *c, const hz_grid *grid, int32_t 
                                         int32_t nviews, float step_len, int32_t reps, double *gather_gbps,
                                         int64_t *samples, void *hip_stream)
 {
-    const char *fn = "hz_membench_gather";
     if (!c || !grid || !views || !gather_gbps) return set_error(HZ_E_INVALID, "hz_membench_gather: NULL argument");
     if (voxel_bytes != 8 && voxel_bytes != 16)
         return set_error(HZ_E_INVALID, "hz_membench_gather: voxel_bytes not 8 or 16");
@@ -181,51 +167,76 @@ extern "C" hz_status hz_membench_gather(hz_ctx *c, const hz_grid *grid, int32_t 
     for (int a = 0; a < 3; ++a) vox = std::min(vox, (grid->hi[a] - grid->lo[a]) / grid->res[a]);
     if (!(step_len >= 1e-3 * vox && step_len <= 1e3 * vox))
         return set_error(HZ_E_INVALID, "hz_membench_gather: step_len outside [1e-3, 1e3] voxels");
+    const size_t fbytes = (size_t)nvox * (size_t)voxel_bytes;
+    if (hipSetDevice(ctx_device(c)) != hipSuccess) return set_error(HZ_E_DEVICE, "hz_membench_gather: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    void *buf = nullptr;
+    hz_status st = ctx_alloc(c, &buf, fbytes);
+    if (st != HZ_OK) return st;
     std::vector<TraceJob> jobs((size_t)nviews);
     int64_t nslots = 0;
     for (int i = 0; i < nviews; ++i) {
-        hz_status st = make_job(&views[i], nullptr, nslots, 0, &jobs[(size_t)i], fn, i);
-        if (st != HZ_OK) return st;
+        st = make_job(&views[i], buf, nslots, 0, &jobs[(size_t)i], "hz_membench_gather", i);
+        if (st != HZ_OK) {
+            ctx_free(c, buf, fbytes);
+            return st;
+        }
         nslots += view_slots(views[i].width, views[i].height);
     }
-    if (nslots > INT32_MAX) return set_error(HZ_E_INVALID, "hz_membench_gather: more than 2^31 - 1 rays");
-    TraceGrid G;
-    make_trace_grid(*grid, 1.0f, &G);
-    if (hipSetDevice(ctx_device(c)) != hipSuccess) return set_error(HZ_E_DEVICE, "hz_membench_gather: hipSetDevice");
-    hipStream_t s = (hipStream_t)hip_stream;
-    const size_t fbytes = (size_t)nvox * (size_t)voxel_bytes;
-    const size_t jbytes = sizeof(TraceJob) * jobs.size();
-    const size_t sbytes = 4u * (size_t)nslots + 256;
-    void *buf = nullptr, *aux = nullptr;
-    hz_status st = ctx_alloc(c, &buf, fbytes);
-    if (st != HZ_OK) return st;
-    st = ctx_alloc(c, &aux, 256 + jbytes + sbytes);
+    if (nslots > INT32_MAX) {
+        ctx_free(c, buf, fbytes);
+        return set_error(HZ_E_INVALID, "hz_membench_gather: more than 2^31 - 1 rays");
+    }
+    // the tracer's ray generation builds the length-sorted hit list (no
+    // outputs: its rays that miss write nothing)
+    const size_t jbytes = (sizeof(TraceJob) * jobs.size() + 255) & ~(size_t)255;
+    const size_t aux_bytes = 256 + jbytes + kCounterBytes + 4 * (size_t)nslots + (size_t)nslots + 4 * (size_t)nslots;
+    void *aux = nullptr;
+    st = ctx_alloc(c, &aux, aux_bytes);
     if (st != HZ_OK) {
         ctx_free(c, buf, fbytes);
         return st;
     }
-    unsigned long long *count = (unsigned long long *)aux;
-    TraceJob *djobs = (TraceJob *)((char *)aux + 256);
-    uint32_t *sink = (uint32_t *)((char *)aux + 256 + jbytes);
+    char *p = (char *)aux;
+    unsigned long long *count = (unsigned long long *)p;
+    TraceJob *djobs = (TraceJob *)(p + 256);
+    uint32_t *counters = (uint32_t *)(p + 256 + jbytes);
+    uint32_t *hits = (uint32_t *)((char *)counters + kCounterBytes);
+    uint8_t *bins = (uint8_t *)(hits + nslots);
+    uint32_t *sink = (uint32_t *)(bins + nslots);
+    TraceLaunch L{};
+    L.jobs = djobs;
+    L.njobs = nviews;
+    L.nslots = nslots;
+    L.hits = hits;
+    L.slot_bin = bins;
+    L.counters = counters;
+    L.counters_next = counters + kCounterSetWords;
+    make_trace_grid(*grid, 1.0f, &L.grid);
+    L.inv_len_bin = length_bin_scale(*grid);
     const int64_t n4 = (int64_t)(fbytes / 16);
-    const dim3 g((unsigned)((nslots + 255) / 256)), b(256);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms = 0.0f;
     unsigned long long total = 0;
+    std::vector<uint32_t> bin_tot((size_t)kCounterSetWords);
     bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-              hipMemcpyAsync(djobs, jobs.data(), jbytes, hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemsetAsync(count, 0, 8, s) == hipSuccess;
-    if (ok) {
+              hipMemcpyAsync(djobs, jobs.data(), sizeof(TraceJob) * jobs.size(), hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              hipMemsetAsync(count, 0, 16, s) == hipSuccess && launch_raygen(L, true, s, KTimer{}) == hipSuccess &&
+              hipMemcpyAsync(bin_tot.data(), counters, 4 * bin_tot.size(), hipMemcpyDeviceToHost, s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess;
+    uint32_t nh = 0;
+    for (int k = 0; ok && k < kRayBins; ++k) nh += bin_tot[(size_t)k * kCounterStride];
+    if (ok && nh > 0) {
+        const dim3 g((nh + 255) / 256), b(256);
         hipLaunchKernelGGL(k_init, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s, (float4 *)buf, n4);
         for (int r = 0; r <= reps; ++r) {   // launch 0 warms the caches and counts the samples
             if (r == 1) ok = hipEventRecord(e0, s) == hipSuccess;
             unsigned long long *cnt = r == 0 ? count : count + 1;
             if (voxel_bytes == 16)
-                hipLaunchKernelGGL(k_gather_views<16>, g, b, 0, s, (const char *)buf, G, (const TraceJob *)djobs,
-                                   nviews, nslots, step_len, sink, cnt);
+                hipLaunchKernelGGL(k_gather_hits<16>, g, b, 0, s, (const char *)buf, L, nh, step_len, sink, cnt);
             else
-                hipLaunchKernelGGL(k_gather_views<8>, g, b, 0, s, (const char *)buf, G, (const TraceJob *)djobs,
-                                   nviews, nslots, step_len, sink, cnt);
+                hipLaunchKernelGGL(k_gather_hits<8>, g, b, 0, s, (const char *)buf, L, nh, step_len, sink, cnt);
         }
         ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
              hipEventElapsedTime(&ms, e0, e1) == hipSuccess && hipGetLastError() == hipSuccess &&
@@ -234,7 +245,8 @@ extern "C" hz_status hz_membench_gather(hz_ctx *c, const hz_grid *grid, int32_t 
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     ctx_free(c, buf, fbytes);
-    ctx_free(c, aux, 256 + jbytes + sbytes);
+    ctx_free(c, aux, aux_bytes);
+    if (ok && nh == 0) return set_error(HZ_E_INVALID, "hz_membench_gather: no ray of the views enters the grid");
     if (!ok || ms <= 0.0f) return set_error(HZ_E_DEVICE, "hz_membench_gather: timing failed");
     if (total == 0) return set_error(HZ_E_INVALID, "hz_membench_gather: no ray of the views enters the grid");
     if (samples) *samples = (int64_t)total;

@@ -1,6 +1,6 @@
-// ray_geom.h -- pinhole rays and the slab test against the grid box, shared
-// by the tracer and the gather microbenchmark that replays its rays
-// (internal).
+// ray_geom.h -- queue slots, pinhole rays and the slab test against the grid
+// box, shared by the tracer and the gather microbenchmark that replays its
+// rays (internal).
 #pragma once
 
 #include "haze_device.h"
@@ -41,6 +41,59 @@ __device__ __forceinline__ bool enter_volume(const TraceGrid &G, const float o[3
     t0 = fmaxf(a, 0.0f);
     if (t1) *t1 = b;
     return true;
+}
+
+// A queue slot's ray: its view (job), pixel and output index.
+struct Ray {
+    int32_t job;
+    int32_t p, q;
+    int64_t out;      // output index (flat index in subset mode, q * W + p otherwise)
+};
+
+// Map a queue slot to its view (job), pixel and output index; false for the
+// padding slots of partial 8x8 tiles.
+__device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, Ray &r)
+{
+    // all slot and ray counts are below 2^31 (checked on the host): 32-bit
+    // division from here on
+    if (L.subset) {
+        const int64_t id = L.ray_ids[slot];
+        int lo = 0, hi = L.njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.jobs[mid].ray_begin <= id)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const TraceJob &J = L.jobs[lo];
+        const int64_t local64 = id - J.ray_begin;
+        if (local64 < 0 || local64 >= (int64_t)J.width * J.height) return false;
+        const int32_t local = (int32_t)local64;
+        r.job = lo;
+        r.q = local / J.width;
+        r.p = local - r.q * J.width;
+        r.out = slot;
+        return true;
+    }
+    int lo = 0, hi = L.njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.jobs[mid].slot_begin <= slot)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const TraceJob &J = L.jobs[lo];
+    const int32_t local = (int32_t)(slot - J.slot_begin);
+    const int32_t tile = local >> 6;
+    const int32_t within = local & 63;
+    const int32_t ty = tile / J.tiles_x;
+    r.job = lo;
+    r.p = (tile - ty * J.tiles_x) * 8 + (within & 7);
+    r.q = ty * 8 + (within >> 3);
+    r.out = r.q * J.width + r.p;
+    return r.p < J.width && r.q < J.height;
 }
 
 }  // namespace haze

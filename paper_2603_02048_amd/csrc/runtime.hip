@@ -42,6 +42,10 @@ hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &)
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 hipError_t launch_put_table(void *dst, const void *src, size_t bytes, hipStream_t s);
 int march_blocks_per_cu(int, int);
+const MeshLaunch &mesh_launch(const hz_mesh *m);
+float mesh_reach(const hz_mesh *m);
+hz_ctx *mesh_ctx(const hz_mesh *m);
+void mesh_use(hz_mesh *m, const CallMark &t);
 }  // namespace haze
 
 using namespace haze;
@@ -131,7 +135,7 @@ struct hz_ctx {
     uint64_t mark_next = 1;
     std::mutex mark_mu;
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
-    int march_bpc_scene[2][3] = {};      // by board mode (outer / inner) and dtype
+    int march_bpc_scene[3][3] = {};      // by scene mode (outer boards / inner boards / mesh) and dtype
     // march tuning (hz_ctx_tune)
     int32_t refill_min = 32;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
@@ -363,6 +367,7 @@ extern "C" hz_status hz_ctx_create(int device, uint64_t hbm_budget_bytes, hz_ctx
         c->march_bpc[d] = march_blocks_per_cu(d, 0);
         c->march_bpc_scene[0][d] = march_blocks_per_cu(d, 1);
         c->march_bpc_scene[1][d] = march_blocks_per_cu(d, 2);
+        c->march_bpc_scene[2][d] = march_blocks_per_cu(d, 3);
     }
     c->pinned.resize(8);
     // the completion-mark events exist from the start, so issuing a mark
@@ -1208,7 +1213,8 @@ static hz_status make_scene(const hz_scene *scene, const hz_grid &g, TraceLaunch
 // L gets everything but the scratch pointers.
 static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews, int32_t max_views,
                                const hz_step *step, const int64_t *ray_ids, int64_t nrays, const hz_trace_out *out,
-                               uint8_t *surface, TraceJob *jobs, TraceLaunch *Lp, const char *fn)
+                               uint8_t *surface, uint32_t *tri_tests, TraceJob *jobs, TraceLaunch *Lp,
+                               const char *fn)
 {
     if (!c || !fc || !views || !out) return fail(HZ_E_INVALID, "%s: NULL argument", fn);
     const hz_field *f = fc;
@@ -1242,7 +1248,7 @@ static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *vie
     L.subset = subset ? 1 : 0;
     L.nslots = subset ? nrays : slot;
     L.ray_ids = ray_ids;
-    L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status, surface};
+    L.flat = TraceOutFlat{out->disp, out->exit_pos, out->exit_dir, out->steps, out->status, surface, tri_tests};
     if (!subset)
         for (int i = 0; i < nviews; ++i) {
             TraceJob &J = jobs[i];
@@ -1253,6 +1259,7 @@ static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *vie
             J.steps = out->steps ? out->steps + base : nullptr;
             J.status = out->status ? out->status + base : nullptr;
             J.surface = surface ? surface + base : nullptr;
+            J.tri_tests = tri_tests ? tri_tests + base : nullptr;
         }
     make_trace_grid(f->grid, f->store_scale, &L.grid);
     make_trace_step(*step, f->grid, &L.step);
@@ -1265,21 +1272,33 @@ static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *vie
 static int march_grid_blocks(const hz_ctx *c, const TraceLaunch &L, int dt)
 {
     const int64_t want_blocks = (L.nslots + 255) / 256;
-    const int fit = L.ninner > 0 ? c->march_bpc_scene[1][dt] : L.nquads > 0 ? c->march_bpc_scene[0][dt]
-                                                                            : c->march_bpc[dt];
+    const int fit = L.mesh.ntris > 0 ? c->march_bpc_scene[2][dt]
+                    : L.ninner > 0   ? c->march_bpc_scene[1][dt]
+                    : L.nquads > 0   ? c->march_bpc_scene[0][dt]
+                                     : c->march_bpc[dt];
     const int bpc = c->blocks_per_cu > 0 ? std::min(c->blocks_per_cu, fit) : fit;
     return (int)std::max<int64_t>(1, std::min<int64_t>(want_blocks, (int64_t)bpc * c->num_cus));
 }
 
 static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
-                            const hz_scene *scene, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
-                            const hz_trace_out *out, uint8_t *surface, void *hip_stream, const char *fn)
+                            const hz_scene *scene, const hz_mesh *mesh, const hz_step *step, const int64_t *ray_ids,
+                            int64_t nrays, const hz_trace_out *out, uint8_t *surface, uint32_t *tri_tests,
+                            void *hip_stream, const char *fn)
 {
     std::vector<TraceJob> jobs((size_t)std::max(0, std::min(nviews, 4096)));
     TraceLaunch L;
-    hz_status st = prepare_trace(c, fc, views, nviews, 4096, step, ray_ids, nrays, out, surface, jobs.data(), &L, fn);
+    hz_status st = prepare_trace(c, fc, views, nviews, 4096, step, ray_ids, nrays, out, surface, tri_tests,
+                                 jobs.data(), &L, fn);
     if (st != HZ_OK) return st;
     hz_field *f = const_cast<hz_field *>(fc);
+    if (mesh) {
+        if (mesh_ctx(mesh) != c) return fail(HZ_E_INVALID, "%s: mesh belongs to another context", fn);
+        const float longest = step->uniform ? step->ds_uniform : step->ds_max;
+        if (longest > mesh_reach(mesh))
+            return fail(HZ_E_INVALID, "%s: steps up to %g m, but the mesh's shell serves steps up to %g m", fn,
+                        (double)longest, (double)mesh_reach(mesh));
+        L.mesh = mesh_launch(mesh);
+    }
     std::vector<SceneQuad> quads;
     st = make_scene(scene, f->grid, &L, quads, fn);
     if (st != HZ_OK) return st;
@@ -1328,6 +1347,7 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     for (Scratch *b : {&c->jobs, &c->hits, &c->bins, &c->counters}) b->last = done;
     staging->last = done;
     field_mark_used(f, done);
+    if (mesh) mesh_use(const_cast<hz_mesh *>(mesh), done);
     return HZ_OK;
 }
 
@@ -1335,16 +1355,25 @@ extern "C" hz_status hz_trace_views(hz_ctx *c, const hz_field *fc, const hz_view
                                     const hz_step *step, const int64_t *ray_ids, int64_t nrays,
                                     const hz_trace_out *out, void *hip_stream)
 {
-    return trace_impl(c, fc, views, nviews, nullptr, step, ray_ids, nrays, out, nullptr, hip_stream,
-                      "hz_trace_views");
+    return trace_impl(c, fc, views, nviews, nullptr, nullptr, step, ray_ids, nrays, out, nullptr, nullptr,
+                      hip_stream, "hz_trace_views");
 }
 
 extern "C" hz_status hz_trace_scene(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
                                     const hz_scene *scene, const hz_step *step, const int64_t *ray_ids,
                                     int64_t nrays, const hz_trace_out *out, uint8_t *surface, void *hip_stream)
 {
-    return trace_impl(c, fc, views, nviews, scene, step, ray_ids, nrays, out, surface, hip_stream,
-                      "hz_trace_scene");
+    return trace_impl(c, fc, views, nviews, scene, nullptr, step, ray_ids, nrays, out, surface, nullptr,
+                      hip_stream, "hz_trace_scene");
+}
+
+extern "C" hz_status hz_trace_mesh(hz_ctx *c, const hz_field *fc, const hz_view *views, int32_t nviews,
+                                   const hz_mesh *mesh, const hz_step *step, const int64_t *ray_ids, int64_t nrays,
+                                   const hz_trace_out *out, uint8_t *surface, uint32_t *tri_tests, void *hip_stream)
+{
+    if (!mesh) return fail(HZ_E_INVALID, "hz_trace_mesh: mesh is NULL");
+    return trace_impl(c, fc, views, nviews, nullptr, mesh, step, ray_ids, nrays, out, surface, tri_tests,
+                      hip_stream, "hz_trace_mesh");
 }
 
 // ---------------------------------------------------------------------------
@@ -1398,8 +1427,8 @@ extern "C" hz_status hz_trace_views_noalloc(hz_ctx *c, const hz_field *fc, const
     const char *fn = "hz_trace_views_noalloc";
     TraceJob jobs[kNoAllocViews];
     TraceLaunch L;
-    hz_status st = prepare_trace(c, fc, views, nviews, kNoAllocViews, step, ray_ids, nrays, out, nullptr, jobs, &L,
-                                 fn);
+    hz_status st = prepare_trace(c, fc, views, nviews, kNoAllocViews, step, ray_ids, nrays, out, nullptr, nullptr,
+                                 jobs, &L, fn);
     if (st != HZ_OK) return st;
     if (L.nslots > kNoAllocSlots)
         return fail(HZ_E_UNSUPPORTED,
@@ -1442,6 +1471,7 @@ float field_scale(const hz_field *f) { return f->store_scale; }
 const void *field_data(const hz_field *f) { return f->data; }
 hz_ctx *field_ctx(const hz_field *f) { return f->ctx; }
 hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out) { return mark_issue(c, s, out); }
+hz_status ctx_mark_sync(hz_ctx *c, const CallMark &t) { return mark_sync(c, t); }
 void field_use(hz_field *f, const CallMark &t) { field_mark_used(f, t); }
 hz_status field_ready(hz_field *f, hipStream_t s) { return field_order_read(f->ctx, f, s); }
 int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }

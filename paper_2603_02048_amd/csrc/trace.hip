@@ -42,58 +42,6 @@
 
 namespace haze {
 
-struct Ray {
-    int32_t job;
-    int32_t p, q;
-    int64_t out;      // output index (flat index in subset mode, q * W + p otherwise)
-};
-
-// Map a queue slot to its view (job), pixel and output index; false for the
-// padding slots of partial 8x8 tiles.
-__device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, Ray &r)
-{
-    // all slot and ray counts are below 2^31 (checked on the host): 32-bit
-    // division from here on
-    if (L.subset) {
-        const int64_t id = L.ray_ids[slot];
-        int lo = 0, hi = L.njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.jobs[mid].ray_begin <= id)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const TraceJob &J = L.jobs[lo];
-        const int64_t local64 = id - J.ray_begin;
-        if (local64 < 0 || local64 >= (int64_t)J.width * J.height) return false;
-        const int32_t local = (int32_t)local64;
-        r.job = lo;
-        r.q = local / J.width;
-        r.p = local - r.q * J.width;
-        r.out = slot;
-        return true;
-    }
-    int lo = 0, hi = L.njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.jobs[mid].slot_begin <= slot)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const TraceJob &J = L.jobs[lo];
-    const int32_t local = (int32_t)(slot - J.slot_begin);
-    const int32_t tile = local >> 6;
-    const int32_t within = local & 63;
-    const int32_t ty = tile / J.tiles_x;
-    r.job = lo;
-    r.p = (tile - ty * J.tiles_x) * 8 + (within & 7);
-    r.q = ty * 8 + (within >> 3);
-    r.out = r.q * J.width + r.p;
-    return r.p < J.width && r.q < J.height;
-}
-
 // Exit distance along w from a point in the volume (clamped at 0).
 __device__ __forceinline__ float exit_distance(const TraceGrid &G, const float c[3], const float w[3])
 {
@@ -202,40 +150,55 @@ __device__ int cast_mesh(const MeshLaunch &M, const float x[3], const float w[3]
         thit = bt;
         return -1;
     }
-    int ci[3], stp[3];
-    float tn[3], td[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    // per-axis walk state in scalars (an array indexed by the axis chosen at
+    // run time would live in private memory)
+    auto axis_start = [&](int a, int &ci, int &stp, float &tn, float &td) {
         const float p = fmaf(ta, w[a], x[a]);
-        ci[a] = min(max((int)floorf((p - M.lo[a]) * M.inv_cell), 0), M.res[a] - 1);
+        ci = min(max((int)floorf((p - M.lo[a]) * M.inv_cell), 0), M.res[a] - 1);
         if (w[a] > 0.0f) {
-            stp[a] = 1;
-            tn[a] = (M.lo[a] + (float)(ci[a] + 1) * M.cell - x[a]) / w[a];
-            td[a] = M.cell / w[a];
+            stp = 1;
+            tn = (M.lo[a] + (float)(ci + 1) * M.cell - x[a]) / w[a];
+            td = M.cell / w[a];
         } else if (w[a] < 0.0f) {
-            stp[a] = -1;
-            tn[a] = (M.lo[a] + (float)ci[a] * M.cell - x[a]) / w[a];
-            td[a] = -M.cell / w[a];
+            stp = -1;
+            tn = (M.lo[a] + (float)ci * M.cell - x[a]) / w[a];
+            td = -M.cell / w[a];
         } else {
-            stp[a] = 0;
-            tn[a] = INFINITY;
-            td[a] = INFINITY;
+            stp = 0;
+            tn = INFINITY;
+            td = INFINITY;
         }
-    }
+    };
+    int cx, cy, cz, sx, sy, sz;
+    float tnx, tny, tnz, tdx, tdy, tdz;
+    axis_start(0, cx, sx, tnx, tdx);
+    axis_start(1, cy, sy, tny, tdy);
+    axis_start(2, cz, sz, tnz, tdz);
+    const int rx = M.res[0], ry = M.res[1], rz = M.res[2];
     float tenter = ta;
-    for (int it = 0; it < M.res[0] + M.res[1] + M.res[2] + 3; ++it) {
+    for (int it = 0; it < rx + ry + rz + 3; ++it) {
         if (tenter > bt) break;
-        const uint32_t cell = ((uint32_t)ci[2] * (uint32_t)M.res[1] + (uint32_t)ci[1]) * (uint32_t)M.res[0] +
-                              (uint32_t)ci[0];
+        const uint32_t cell = ((uint32_t)cz * (uint32_t)ry + (uint32_t)cy) * (uint32_t)rx + (uint32_t)cx;
         const uint32_t e0 = M.start[cell], e1 = M.start[cell + 1];
         for (uint32_t e = e0; e < e1; ++e) cast_tri(M, (int)M.list[e], x, w, best, bt);
         ntests += e1 - e0;
-        const int a = tn[0] <= tn[1] ? (tn[0] <= tn[2] ? 0 : 2) : (tn[1] <= tn[2] ? 1 : 2);
-        tenter = tn[a];
+        if (tnx <= tny && tnx <= tnz) {
+            tenter = tnx;
+            cx += sx;
+            tnx += tdx;
+            if (cx < 0 || cx >= rx) break;
+        } else if (tny <= tnz) {
+            tenter = tny;
+            cy += sy;
+            tny += tdy;
+            if (cy < 0 || cy >= ry) break;
+        } else {
+            tenter = tnz;
+            cz += sz;
+            tnz += tdz;
+            if (cz < 0 || cz >= rz) break;
+        }
         if (tenter > tb) break;
-        ci[a] += stp[a];
-        if (ci[a] < 0 || ci[a] >= M.res[a]) break;
-        tn[a] += td[a];
     }
     thit = bt;
     return best;

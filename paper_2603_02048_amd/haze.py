@@ -73,10 +73,19 @@ class hz_scene(C.Structure):
     _fields_ = [("nquads", C.c_int32), ("quads", C.POINTER(hz_quad))]
 
 
+class hz_triangle(C.Structure):
+    _fields_ = [("v0", C.c_float * 3), ("v1", C.c_float * 3), ("v2", C.c_float * 3), ("surface", C.c_int32)]
+
+
+class hz_mesh_params(C.Structure):
+    _fields_ = [("reach", C.c_float), ("cell", C.c_float), ("brute_force", C.c_int32)]
+
+
 EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", "hz_ctx_tune", "hz_profile_enable",
            "hz_profile_select", "hz_profile_read", "hz_membench", "hz_membench_gather", "hz_splat_index_field",
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
-           "hz_trace_views_noalloc", "hz_trace_scene",
+           "hz_trace_views_noalloc", "hz_trace_scene", "hz_mesh_create", "hz_mesh_info", "hz_mesh_release",
+           "hz_trace_mesh",
            "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_timing",
            "hz_request_release", "hz_server_stop"]
 
@@ -124,6 +133,16 @@ def lib():
         L.hz_trace_scene.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_scene), C.POINTER(hz_step),
                                      P, C.c_int64, C.POINTER(hz_trace_out), P, P]
         L.hz_trace_scene.restype = S
+        L.hz_mesh_create.argtypes = [P, C.POINTER(hz_triangle), C.c_int32, C.POINTER(hz_mesh_params), P,
+                                     C.POINTER(C.c_void_p)]
+        L.hz_mesh_create.restype = S
+        L.hz_mesh_info.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_float),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+        L.hz_mesh_info.restype = S
+        L.hz_mesh_release.argtypes, L.hz_mesh_release.restype = [P, P], S
+        L.hz_trace_mesh.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, P, C.POINTER(hz_step), P, C.c_int64,
+                                    C.POINTER(hz_trace_out), P, P, P]
+        L.hz_trace_mesh.restype = S
         L.hz_server_start.argtypes, L.hz_server_start.restype = [P, C.c_int32, C.c_int64], S
         L.hz_submit.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), C.POINTER(C.c_uint64)]
         L.hz_submit.restype = S
@@ -231,6 +250,26 @@ class Field:
     def release(self):
         if self.handle:
             _check(lib().hz_field_release(C.c_void_p(self.ctx.handle), C.c_void_p(self.handle)), "field_release")
+            self.handle = 0
+
+
+class Mesh:
+    """A device-resident triangle-mesh scene with its conservative shell."""
+
+    def __init__(self, ctx: "Context", handle: int):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self) -> dict:
+        n, res, cell, ent, nb = C.c_int32(), (C.c_int32 * 3)(), C.c_float(), C.c_int64(), C.c_uint64()
+        _check(lib().hz_mesh_info(C.c_void_p(self.handle), C.byref(n), res, C.byref(cell), C.byref(ent),
+                                  C.byref(nb)), "mesh_info")
+        return dict(ntris=n.value, shell_res=tuple(res), shell_cell=cell.value, list_entries=ent.value,
+                    bytes=nb.value)
+
+    def release(self):
+        if self.handle:
+            _check(lib().hz_mesh_release(C.c_void_p(self.ctx.handle), C.c_void_p(self.handle)), "mesh_release")
             self.handle = 0
 
 
@@ -383,6 +422,44 @@ class Context:
         _check(lib().hz_trace_scene(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
                                     len(views), C.byref(sc), C.byref(make_step(step)), _ptr(ray_ids), n,
                                     C.byref(o), _ptr(out["surface"]), _stream(stream)), "trace_scene")
+        return out
+
+    def mesh_create(self, tris, surfaces, reach: float, cell: float = 0.0, brute_force: bool = False,
+                    stream=None) -> Mesh:
+        """A mesh scene from (T, 3, 3) triangle vertices and (T,) surface ids."""
+        v = np.asarray(tris, np.float32).reshape(-1, 3, 3)
+        sf = np.asarray(surfaces, np.int64).reshape(-1)
+        arr = (hz_triangle * max(1, v.shape[0]))()
+        for i in range(v.shape[0]):
+            arr[i] = hz_triangle((C.c_float * 3)(*v[i, 0]), (C.c_float * 3)(*v[i, 1]), (C.c_float * 3)(*v[i, 2]),
+                                 int(sf[i]))
+        prm = hz_mesh_params(float(reach), float(cell), 1 if brute_force else 0)
+        out = C.c_void_p()
+        _check(lib().hz_mesh_create(C.c_void_p(self.handle), arr, v.shape[0], C.byref(prm), _stream(stream),
+                                    C.byref(out)), "mesh_create")
+        return Mesh(self, out.value)
+
+    def trace_mesh(self, field: Field, views: Sequence, mesh: Mesh, step, ray_ids: Optional[torch.Tensor] = None,
+                   out: Optional[dict] = None, count_tests: bool = False, stream=None) -> dict:
+        """trace_views against a triangle mesh: outputs gain `surface` (uint8: 0
+        backdrop, s + 1 surface s, 255 none) and, with count_tests, `tri_tests`
+        (exact ray-triangle tests per ray)."""
+        total = sum(int(v.width) * int(v.height) for v in views)
+        n = total if ray_ids is None else int(ray_ids.numel())
+        if out is None:
+            out = alloc_outputs(n)
+        dev = out["status"].device
+        if "surface" not in out:
+            out["surface"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        if count_tests and "tri_tests" not in out:
+            out["tri_tests"] = torch.empty(n, dtype=torch.int32, device=dev)
+        o = hz_trace_out(_ptr(out.get("disp")), _ptr(out.get("exit_pos")), _ptr(out.get("exit_dir")),
+                         _ptr(out.get("steps")), _ptr(out.get("status")))
+        if ray_ids is not None:
+            assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
+        _check(lib().hz_trace_mesh(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views), len(views),
+                                   C.c_void_p(mesh.handle), C.byref(make_step(step)), _ptr(ray_ids), n, C.byref(o),
+                                   _ptr(out["surface"]), _ptr(out.get("tri_tests")), _stream(stream)), "trace_mesh")
         return out
 
     # -- serving ----------------------------------------------------------

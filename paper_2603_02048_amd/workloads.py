@@ -437,3 +437,38 @@ def serving_requests(lo, hi, duration_s: float, rate_hz: float = 200.0, nframes:
         views = [ring_view(lo, hi, ph + 2.0 * math.pi * k / nv, rad, w, h) for k in range(nv)]
         out.append(Request(t_arrive=t, frame=frame, views=views))
     return out
+
+
+def tessellate_quads(quads, n: int = 4):
+    """Scene boards as triangle meshes: each parallelogram (origin, edge_u,
+    edge_v) cut into n x n cells of two triangles, all of the board's surface
+    id (its index).  Returns (T, 3, 3) float64 vertices and (T,) surface ids."""
+    tris, surf = [], []
+    for k, (o, eu, ev) in enumerate(np.asarray(quads, np.float64)):
+        def p(i, j):
+            return o + (i / n) * eu + (j / n) * ev
+        for i in range(n):
+            for j in range(n):
+                a, b, c, d = p(i, j), p(i + 1, j), p(i + 1, j + 1), p(i, j + 1)
+                tris += [(a, b, c), (a, c, d)]
+                surf += [k, k]
+    return np.asarray(tris, np.float64), np.asarray(surf, np.int64)
+
+
+def icosphere(centre, radius: float, subdiv: int = 2):
+    """Triangles of a sphere: an icosahedron whose faces are split in four
+    `subdiv` times, vertices pushed onto the sphere.  (T, 3, 3) float64."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    tris = [tuple(np.asarray(v[i], float) / np.linalg.norm(v[i]) for i in face) for face in f]
+    for _ in range(subdiv):
+        nxt = []
+        for a, b, c in tris:
+            ab, bc, ca = [(x + y) / np.linalg.norm(x + y) for x, y in ((a, b), (b, c), (c, a))]
+            nxt += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        tris = nxt
+    return np.asarray(centre, np.float64) + radius * np.asarray(tris, np.float64)
