@@ -106,7 +106,8 @@ def per_view_steps(out, wl) -> list:
     return res
 
 
-def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat",), live_every: int = 4):
+def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat",), live_every: int = 4,
+               latency_samples: int = LATENCY_SAMPLES):
     """ms per step over exactly `steps` steps (host clock between two device
     synchronisations) with the `live` kernel groups timed by their own
     dispatch events inside those steps (every `live_every`-th step, the first
@@ -132,7 +133,7 @@ def time_steps(ctx, torch, fn, steps: int, warmup: int, kernels=(), live=("splat
     ctx.profile_read("march", reset=True)
     ctx.profile_select(None)
     ctx.profile_enable(True)
-    nlat = max(steps, LATENCY_SAMPLES)
+    nlat = max(steps, latency_samples)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(nlat + 1)]
     ev[0].record(stream)
     for i in range(nlat):
@@ -452,6 +453,8 @@ def main(argv=None):
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--no-equal-error", action="store_true", help="skip the equal-error protocol of the oracle leg")
+    ap.add_argument("--latency-samples", type=int, default=LATENCY_SAMPLES,
+                    help="steps of the latency pass (at least --steps); fewer under a profiler")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -501,7 +504,8 @@ def main(argv=None):
     ctx.tune("splat.method", 2 if args.splat == "scatter" else 1)
     res = {}
     for name, st in (("adaptive", st_a), ("uniform", st_u)):
-        ms, per, kt = time_steps(ctx, torch, make_step(st), args.steps, args.warmup, kernels)
+        ms, per, kt = time_steps(ctx, torch, make_step(st), args.steps, args.warmup, kernels,
+                                 latency_samples=args.latency_samples)
         steps_total = int(out["steps"].sum().item())
         hits = int((out["steps"] > 0).sum().item())
         res[name] = dict(ms=ms, per=per, kt=kt, steps=steps_total, hits=hits, per_view=per_view_steps(out, wl))

@@ -103,6 +103,10 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *                          idle, 1..64 (default 32)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
+ *   "march.thin"           1: with F32 fields and more rays than the resident
+ *                          lanes, a third of the march's workgroups exit at
+ *                          once (fewer gathers in flight); 0: all march
+ *                          (default 1)
  *   "splat.method"         0 or 1: gather (one workgroup per 8x8xBZ voxel
  *                          brick, fixed FP32 summation order; the default), 2: scatter
  *                          (voxel tiles with 64-bit fixed-point accumulation in
@@ -450,6 +454,13 @@ hz_status hz_server_start(hz_ctx *ctx, int32_t slots, int64_t max_batch_rays);
 hz_status hz_submit(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
                     const hz_step *step, hz_ticket *out);
 
+/* hz_submit with scene boards (as hz_trace_scene; `scene` is copied).  Only
+ * requests with the same boards (and grid, storage type and step control)
+ * share a launch.  Errors: as hz_submit, and as hz_trace_scene for the
+ * boards. */
+hz_status hz_submit_scene(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                          const hz_scene *scene, const hz_step *step, hz_ticket *out);
+
 /* Poll a request: HZ_PENDING until its results are complete on the device,
  * then HZ_OK with *latency_s = seconds from submit to completion (may be
  * NULL).  Errors: HZ_E_NOTFOUND (unknown or already released ticket),
@@ -460,6 +471,12 @@ hz_status hz_poll(hz_ctx *ctx, hz_ticket ticket, double *latency_s);
  * ray_ids == NULL); valid until hz_request_release.  *nrays gets the number
  * of rays.  Errors: HZ_E_NOTFOUND, HZ_E_INVALID (not complete yet). */
 hz_status hz_request_outputs(hz_ctx *ctx, hz_ticket ticket, hz_trace_out *out, int64_t *nrays);
+
+/* Device array (uint8, one per ray) of the surface each ray of a completed
+ * request met, as hz_trace_scene's `surface` (0 backdrop, k + 1 board k, 255
+ * nothing); valid until hz_request_release.  Errors: HZ_E_NOTFOUND,
+ * HZ_E_INVALID (not complete). */
+hz_status hz_request_surface(hz_ctx *ctx, hz_ticket ticket, uint8_t **surface);
 
 /* Device timestamps (milliseconds from the server's start, on the GPU's own
  * clock) of the first and last kernel of the launch that carried a completed

@@ -139,6 +139,7 @@ struct hz_ctx {
     // march tuning (hz_ctx_tune)
     int32_t refill_min = 32;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
+    int32_t march_thin = 1;      // F32 with more rays than lanes: a third of the workgroups exit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8
     int32_t scan_fault_test = 0; // 1: the one-pass scan's waits give up (fault test)
@@ -616,6 +617,9 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
     if (k == "march.refill_min") {
         if (value < 1 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.refill_min must be in [1, 64]");
         c->refill_min = (int32_t)value;
+    } else if (k == "march.thin") {
+        if (value != 0 && value != 1) return fail(HZ_E_INVALID, "hz_ctx_tune: march.thin must be 0 or 1");
+        c->march_thin = (int32_t)value;
     } else if (k == "march.blocks_per_cu") {
         if (value < 0 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.blocks_per_cu must be in [0, 64]");
         c->blocks_per_cu = (int32_t)value;
@@ -1264,6 +1268,7 @@ static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *vie
     make_trace_grid(f->grid, f->store_scale, &L.grid);
     make_trace_step(*step, f->grid, &L.step);
     L.refill_min = c->refill_min;
+    L.thin = c->march_thin;
     L.inv_len_bin = length_bin_scale(f->grid);
     return HZ_OK;
 }
@@ -1474,7 +1479,15 @@ hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out) { return mark_issue(
 hz_status ctx_mark_sync(hz_ctx *c, const CallMark &t) { return mark_sync(c, t); }
 void field_use(hz_field *f, const CallMark &t) { field_mark_used(f, t); }
 hz_status field_ready(hz_field *f, hipStream_t s) { return field_order_read(f->ctx, f, s); }
-int march_blocks(hz_ctx *c, int dt) { return c->march_bpc[dt] * c->num_cus; }
+int march_blocks(hz_ctx *c, int dt, int scene_mode)
+{
+    return (scene_mode == 0 ? c->march_bpc[dt] : c->march_bpc_scene[scene_mode - 1][dt]) * c->num_cus;
+}
+hz_status build_scene(const hz_scene *scene, const hz_grid &g, TraceLaunch *L, std::vector<SceneQuad> &qs,
+                      const char *fn)
+{
+    return make_scene(scene, g, L, qs, fn);
+}
 // A time measured by the caller's own events, added to a group's sums when
 // profiling is on and the group selected.
 void profile_add(hz_ctx *c, const char *name, double ms)

@@ -36,6 +36,8 @@ namespace haze {
 hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 hz_status check_step(const hz_step *st, const char *fn);
+hz_status build_scene(const hz_scene *scene, const hz_grid &g, TraceLaunch *L, std::vector<SceneQuad> &qs,
+                      const char *fn);
 hz_status make_job(const hz_view *v, const void *field, int64_t slot_begin, int64_t ray_begin, TraceJob *J,
                    const char *fn, int index);
 void make_trace_grid(const hz_grid &g, float store_scale, TraceGrid *G);
@@ -48,12 +50,14 @@ struct Request {
     hz_ticket id = 0;
     hz_field *field = nullptr;
     std::vector<hz_view> views;
+    std::vector<hz_quad> quads;   // scene boards (none: the backdrop only)
     hz_step step{};
     BatchKey key = zero_key();
     int64_t nrays = 0, nslots = 0, out_bytes = 0;
     void *out_mem = nullptr;
     size_t out_cap = 0;         // size class of out_mem
     hz_trace_out out{};
+    uint8_t *surface = nullptr;  // surface each ray met (after status in out_mem)
     double t_submit = 0.0, t_done = 0.0;
     double dev_start_ms = 0.0, dev_end_ms = 0.0;   // its launch on the device, from the server's reference
     int state = REQ_PENDING;
@@ -110,7 +114,7 @@ static double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-static BatchKey make_key(const hz_field *f, const hz_step &st)
+static BatchKey make_key(const hz_field *f, const hz_step &st, const std::vector<hz_quad> &quads)
 {
     BatchKey k = zero_key();
     const hz_grid &g = field_grid(f);
@@ -129,6 +133,13 @@ static BatchKey make_key(const hz_field *f, const hz_step &st)
     k.ds_uniform = st.ds_uniform;
     k.max_steps = st.max_steps;
     k.tau_term = st.tau_term;
+    k.nquads = (int32_t)quads.size();
+    for (size_t q = 0; q < quads.size(); ++q)
+        for (int a = 0; a < 3; ++a) {
+            k.quads[q][a] = quads[q].origin[a];
+            k.quads[q][3 + a] = quads[q].edge_u[a];
+            k.quads[q][6 + a] = quads[q].edge_v[a];
+        }
     return k;
 }
 
@@ -182,6 +193,7 @@ static hz_status alloc_outputs(Server *S, Request *r)
     r->out.exit_dir = (float *)(base + 20 * n);
     r->out.steps = (uint32_t *)(base + 32 * n);
     r->out.status = (uint8_t *)(base + 36 * n);
+    r->surface = (uint8_t *)(base + 37 * n);
     return HZ_OK;
 }
 
@@ -201,6 +213,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
             J.exit_dir = r->out.exit_dir + 3 * local_ray;
             J.steps = r->out.steps + local_ray;
             J.status = r->out.status + local_ray;
+            J.surface = r->surface + local_ray;
             jobs.push_back(J);
             const int64_t nr = (int64_t)r->views[i].width * r->views[i].height;
             slot += view_slots(r->views[i].width, r->views[i].height);
@@ -208,7 +221,17 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
             local_ray += nr;
         }
     }
-    const size_t job_bytes = sizeof(TraceJob) * jobs.size();
+    // the batch's boards (all its requests share them: same key) after the views
+    Request *head = batch[0];
+    TraceLaunch L{};
+    std::vector<SceneQuad> qs;
+    if (!head->quads.empty()) {
+        hz_scene sc{(int32_t)head->quads.size(), head->quads.data()};
+        hz_status st = build_scene(&sc, field_grid(head->field), &L, qs, "serve");
+        if (st != HZ_OK) return st;
+    }
+    const size_t view_bytes = sizeof(TraceJob) * jobs.size();
+    const size_t job_bytes = view_bytes + sizeof(SceneQuad) * qs.size();
     if (sl.jobs_cap < job_bytes) {
         // the slot is idle, so its old table is no longer read; it is freed
         // later with the lock dropped
@@ -234,13 +257,13 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
         if (st != HZ_OK) return st;
     }
     // the slot is idle, so its previous copy out of `pinned` has completed
-    std::memcpy(sl.pinned, jobs.data(), job_bytes);
+    std::memcpy(sl.pinned, jobs.data(), view_bytes);
+    if (!qs.empty()) std::memcpy((char *)sl.pinned + view_bytes, qs.data(), sizeof(SceneQuad) * qs.size());
     if (hipMemcpyAsync(sl.jobs, sl.pinned, job_bytes, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
         return set_error(HZ_E_DEVICE, "serve: hipMemcpyAsync failed");
 
-    Request *head = batch[0];
-    TraceLaunch L{};
     L.jobs = (const TraceJob *)sl.jobs;
+    L.quads = qs.empty() ? nullptr : (const SceneQuad *)((const char *)sl.jobs + view_bytes);
     L.njobs = (int32_t)jobs.size();
     L.subset = 0;
     L.nslots = slot;
@@ -253,8 +276,10 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
     make_trace_step(head->step, field_grid(head->field), &L.step);
     L.refill_min = 32;
+    L.thin = 1;
     const int dt = (int)field_dtype(head->field);
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt)));
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt, L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0)));
     const bool clear = !sl.counters_clean;
     sl.counters_clean = false;
     // the dispatch packets of the first and last kernel record the batch's
@@ -474,10 +499,9 @@ extern "C" hz_status hz_server_stop(hz_ctx *c)
     return HZ_OK;
 }
 
-extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
-                               const hz_step *step, hz_ticket *out)
+static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
+                             const hz_scene *scene, const hz_step *step, hz_ticket *out, const char *fn)
 {
-    const char *fn = "hz_submit";
     if (!c || !f || !views || !out) return set_error(HZ_E_INVALID, "hz_submit: NULL argument");
     Server *S = ctx_server(c);
     if (!S) return set_error(HZ_E_INVALID, "hz_submit: no server running (hz_server_start)");
@@ -487,9 +511,16 @@ extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *view
     if (st != HZ_OK) return st;
     st = field_usable(c, f, fn);
     if (st != HZ_OK) return st;
+    if (scene && scene->nquads > 0) {   // the boards are checked now, not at launch
+        TraceLaunch probe{};
+        std::vector<SceneQuad> qs;
+        st = build_scene(scene, field_grid(f), &probe, qs, fn);
+        if (st != HZ_OK) return st;
+    }
     Request *r = new Request();
     r->field = const_cast<hz_field *>(f);
     r->views.assign(views, views + nviews);
+    if (scene && scene->nquads > 0) r->quads.assign(scene->quads, scene->quads + scene->nquads);
     r->step = *step;
     for (int i = 0; i < nviews; ++i) {
         TraceJob J;
@@ -502,7 +533,7 @@ extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *view
         r->nslots += view_slots(views[i].width, views[i].height);
     }
     r->out_bytes = r->nrays * kOutBytesPerRay;
-    r->key = make_key(f, *step);
+    r->key = make_key(f, *step, r->quads);
     uint64_t budget = 0;
     hz_ctx_memory(c, nullptr, &budget);
     if (r->nslots > S->slot_capacity || (uint64_t)out_class(r->out_bytes) > budget) {
@@ -519,6 +550,18 @@ extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *view
     }
     S->cv.notify_all();
     return HZ_OK;
+}
+
+extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
+                               const hz_step *step, hz_ticket *out)
+{
+    return submit_impl(c, f, views, nviews, nullptr, step, out, "hz_submit");
+}
+
+extern "C" hz_status hz_submit_scene(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
+                                     const hz_scene *scene, const hz_step *step, hz_ticket *out)
+{
+    return submit_impl(c, f, views, nviews, scene, step, out, "hz_submit_scene");
 }
 
 extern "C" hz_status hz_poll(hz_ctx *c, hz_ticket t, double *latency_s)
@@ -548,6 +591,20 @@ extern "C" hz_status hz_request_outputs(hz_ctx *c, hz_ticket t, hz_trace_out *ou
     if (r->state != REQ_DONE) return set_error(HZ_E_INVALID, "hz_request_outputs: the request is not complete");
     *out = r->out;
     if (nrays) *nrays = r->nrays;
+    return HZ_OK;
+}
+
+extern "C" hz_status hz_request_surface(hz_ctx *c, hz_ticket t, uint8_t **surface)
+{
+    if (!c || !surface) return set_error(HZ_E_INVALID, "hz_request_surface: NULL argument");
+    Server *S = ctx_server(c);
+    if (!S) return set_error(HZ_E_INVALID, "hz_request_surface: no server running");
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) return set_error(HZ_E_NOTFOUND, "hz_request_surface: unknown ticket");
+    if (it->second->state != REQ_DONE)
+        return set_error(HZ_E_INVALID, "hz_request_surface: the request is not complete");
+    *surface = it->second->surface;
     return HZ_OK;
 }
 

@@ -9,7 +9,9 @@
 namespace haze {
 
 // What decides whether two requests can share one launch: the tracer's
-// launch-uniform data (grid geometry, storage type and scale, step control).
+// launch-uniform data (grid geometry, storage type and scale, step control,
+// scene boards: each as origin, edge_u, edge_v).
+constexpr int kKeyQuads = 8;
 struct BatchKey {
     double lo[3], hi[3];
     int32_t res[3];
@@ -19,6 +21,8 @@ struct BatchKey {
     float theta_max, ds_min, ds_max, eps, ds_uniform;
     int32_t max_steps;
     float tau_term;
+    int32_t nquads;
+    float quads[kKeyQuads][9];
 };
 
 inline bool same_key(const BatchKey &a, const BatchKey &b)
@@ -74,7 +78,7 @@ inline int64_t view_slots(int32_t width, int32_t height)
 }
 
 // Device bytes of one ray's outputs: disp (2 f32), exit_pos (3 f32),
-// exit_dir (3 f32), steps (u32), status (u8).
-constexpr int64_t kOutBytesPerRay = 8 + 12 + 12 + 4 + 1;
+// exit_dir (3 f32), steps (u32), status (u8), surface (u8).
+constexpr int64_t kOutBytesPerRay = 8 + 12 + 12 + 4 + 1 + 1;
 
 }  // namespace haze

@@ -642,7 +642,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
     // workgroups however they were placed, and the rest are renumbered
     // densely.  With fewer rays, every wave keeps its static batch.
     uint32_t blk = blockIdx.x, nblk = gridDim.x;
-    if (DT == DT_F32 && SCENE != 2 && ((nh + 63u) >> 6) > nblk * (blockDim.x >> 6)) {
+    if (DT == DT_F32 && SCENE != 2 && L.thin && ((nh + 63u) >> 6) > nblk * (blockDim.x >> 6)) {
         if (blk % 3u == 2u) return;
         blk = 2u * (blk / 3u) + blk % 3u;
         nblk = 2u * (nblk / 3u) + min(nblk % 3u, 2u);
@@ -894,8 +894,12 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
 // Without boards, or with boards only outside the volume, the march fits six
 // waves per SIMD (at most 80 VGPRs) with no spills; the board-crossing
 // variant fits five (capped at six, it would spill).
+#ifndef HZ_MARCH_F32_WAVES
+#define HZ_MARCH_F32_WAVES 6
+#endif
 template <int DT, int SCENE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_march(TraceLaunch L)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DT == DT_F32 ? HZ_MARCH_F32_WAVES : 6)))
+void k_march(TraceLaunch L)
 {
     march<DT, SCENE>(L);
 }

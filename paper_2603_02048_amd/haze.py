@@ -86,8 +86,8 @@ EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", 
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_trace_views_noalloc", "hz_trace_scene", "hz_mesh_create", "hz_mesh_info", "hz_mesh_release",
            "hz_trace_mesh",
-           "hz_server_start", "hz_submit", "hz_poll", "hz_request_outputs", "hz_request_timing",
-           "hz_request_release", "hz_server_stop"]
+           "hz_server_start", "hz_submit", "hz_submit_scene", "hz_poll", "hz_request_outputs",
+           "hz_request_surface", "hz_request_timing", "hz_request_release", "hz_server_stop"]
 
 _lib = None
 
@@ -146,6 +146,11 @@ def lib():
         L.hz_server_start.argtypes, L.hz_server_start.restype = [P, C.c_int32, C.c_int64], S
         L.hz_submit.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_step), C.POINTER(C.c_uint64)]
         L.hz_submit.restype = S
+        L.hz_submit_scene.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_scene), C.POINTER(hz_step),
+                                      C.POINTER(C.c_uint64)]
+        L.hz_submit_scene.restype = S
+        L.hz_request_surface.argtypes = [P, C.c_uint64, C.POINTER(C.c_void_p)]
+        L.hz_request_surface.restype = S
         L.hz_poll.argtypes, L.hz_poll.restype = [P, C.c_uint64, C.POINTER(C.c_double)], S
         L.hz_request_outputs.argtypes = [P, C.c_uint64, C.POINTER(hz_trace_out), C.POINTER(C.c_int64)]
         L.hz_request_outputs.restype = S
@@ -412,11 +417,7 @@ class Context:
             out["surface"] = torch.empty(n, dtype=torch.uint8, device=out["status"].device)
         o = hz_trace_out(_ptr(out.get("disp")), _ptr(out.get("exit_pos")), _ptr(out.get("exit_dir")),
                          _ptr(out.get("steps")), _ptr(out.get("status")))
-        q = np.asarray(quads, np.float32).reshape(-1, 3, 3)
-        arr = (hz_quad * max(1, q.shape[0]))()
-        for k in range(q.shape[0]):
-            arr[k] = hz_quad((C.c_float * 3)(*q[k, 0]), (C.c_float * 3)(*q[k, 1]), (C.c_float * 3)(*q[k, 2]))
-        sc = hz_scene(q.shape[0], arr)
+        sc, _keep = _make_scene(quads)
         if ray_ids is not None:
             assert ray_ids.dtype == torch.int64 and ray_ids.is_cuda and ray_ids.is_contiguous()
         _check(lib().hz_trace_scene(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
@@ -466,10 +467,17 @@ class Context:
     def server_start(self, slots: int = 4, max_batch_rays: int = 1 << 23):
         _check(lib().hz_server_start(C.c_void_p(self.handle), int(slots), int(max_batch_rays)), "server_start")
 
-    def submit(self, field: Field, views: Sequence, step) -> int:
+    def submit(self, field: Field, views: Sequence, step, quads=None) -> int:
+        """Submit a request (with scene boards `quads`, (K, 3, 3), if given)."""
         t = C.c_uint64()
-        _check(lib().hz_submit(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views), len(views),
-                               C.byref(make_step(step)), C.byref(t)), "submit")
+        if quads is None:
+            _check(lib().hz_submit(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views), len(views),
+                                   C.byref(make_step(step)), C.byref(t)), "submit")
+        else:
+            sc, _keep = _make_scene(quads)
+            _check(lib().hz_submit_scene(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
+                                         len(views), C.byref(sc), C.byref(make_step(step)), C.byref(t)),
+                   "submit_scene")
         return t.value
 
     def poll(self, ticket: int) -> Optional[float]:
@@ -485,7 +493,10 @@ class Context:
         n = C.c_int64()
         _check(lib().hz_request_outputs(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(o), C.byref(n)),
                "request_outputs")
-        return _wrap_device_outputs(o, n.value, copy)
+        sp = C.c_void_p()
+        _check(lib().hz_request_surface(C.c_void_p(self.handle), C.c_uint64(ticket), C.byref(sp)),
+               "request_surface")
+        return _wrap_device_outputs(o, n.value, copy, sp.value)
 
     def request_timing(self, ticket: int) -> tuple:
         """(device start ms, device end ms) of the launch that carried a
@@ -500,6 +511,15 @@ class Context:
 
     def server_stop(self):
         _check(lib().hz_server_stop(C.c_void_p(self.handle)), "server_stop")
+
+
+def _make_scene(quads):
+    """hz_scene of (K, 3, 3) boards; returns the struct and the array it points to."""
+    q = np.asarray(quads, np.float32).reshape(-1, 3, 3)
+    arr = (hz_quad * max(1, q.shape[0]))()
+    for k in range(q.shape[0]):
+        arr[k] = hz_quad((C.c_float * 3)(*q[k, 0]), (C.c_float * 3)(*q[k, 1]), (C.c_float * 3)(*q[k, 2]))
+    return hz_scene(q.shape[0], arr), arr
 
 
 def alloc_outputs(n: int, device="cuda") -> dict:
@@ -518,11 +538,13 @@ class _DeviceArray:
                                          "version": 2, "strides": None}
 
 
-def _wrap_device_outputs(o: hz_trace_out, n: int, copy: bool = True) -> dict:
+def _wrap_device_outputs(o: hz_trace_out, n: int, copy: bool = True, surface: Optional[int] = None) -> dict:
     """Torch tensors over a request's library-owned outputs (cloned by default,
-    since the library frees them at request_release)."""
+    since the library reuses them after request_release)."""
     spec = [("disp", o.disp, (n, 2), "<f4"), ("exit_pos", o.exit_pos, (n, 3), "<f4"),
             ("exit_dir", o.exit_dir, (n, 3), "<f4"), ("steps", o.steps, (n,), "<i4"), ("status", o.status, (n,), "|u1")]
+    if surface:
+        spec.append(("surface", surface, (n,), "|u1"))
     out = {}
     for name, ptr, shape, ts in spec:
         t = torch.as_tensor(_DeviceArray(ptr, shape, ts), device="cuda")

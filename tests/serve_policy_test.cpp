@@ -61,12 +61,25 @@ int main()
         for (int i = 0; i < 20; ++i) q.push_back(req(3, 1, 1));
         CHECK(plan_batch(q, 100, 1000, 5).size() == 5);
     }
+    // requests with different scene boards never share a launch
+    {
+        std::vector<PendingInfo> q = {req(1, 10, 10), req(1, 10, 10), req(1, 10, 10)};
+        q[1].key.nquads = 1;
+        q[1].key.quads[0][4] = 0.5f;
+        q[2].key.nquads = 1;
+        q[2].key.quads[0][4] = 0.5f;
+        auto p = plan_batch(q, 100, 1000, 8);
+        CHECK(p.size() == 1 && p[0] == 0);
+        std::vector<PendingInfo> r(q.begin() + 1, q.end());
+        auto p2 = plan_batch(r, 100, 1000, 8);
+        CHECK(p2.size() == 2);
+    }
     // slot counting: 8x8 tiles of 64 slots, ragged edges padded
     CHECK(view_slots(8, 8) == 64);
     CHECK(view_slots(9, 8) == 128);
     CHECK(view_slots(1280, 720) == 1280 * 720);
     CHECK(view_slots(37, 23) == 5 * 3 * 64);
-    CHECK(kOutBytesPerRay == 37);
+    CHECK(kOutBytesPerRay == 38);   // disp, exit_pos, exit_dir, steps, status, surface
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
     return failures ? 1 : 0;
 }

@@ -94,7 +94,7 @@ def test_serve_budget_admission_and_errors(haze):
     wl = W.make_small(seed=3, n=3000, width=8, height=8, nviews=1)
     # budget: the field, one launch slot's scratch and outputs for ~1.5 requests
     views = [W.ring_view(wl.grid.lo, wl.grid.hi, 0.3, 1.2, 256, 128)]
-    per_req = 256 * 128 * 37
+    per_req = 256 * 128 * 38
     probe = haze.Context(0)
     f0 = probe.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
     used_with_field, _ = probe.memory()
@@ -177,6 +177,44 @@ def test_serve_slots_overlap_on_device(haze):
             ctx.request_release(ta)
             ctx.request_release(tb)
         assert min(overlaps) > 0.2, overlaps
+        ctx.server_stop()
+    finally:
+        ctx.close()
+
+
+def test_serve_scene_boards_mix_equals_solo(haze):
+    """Requests with scene boards (hz_submit_scene) and without, interleaved:
+    each result bitwise equal to a solo hz_trace_scene of the same views and
+    boards (no boards: the backdrop only, surface 0 or 255)."""
+    from tests.test_gpu_scene import _boards
+    print("case serve scene boards: 18 requests, three board sets and none", flush=True)
+    ctx = haze.Context(0)
+    try:
+        frames = _frames(ctx, haze, n=2)
+        grid = frames[0][0].grid
+        st_a, st_u = W.make_steps(grid)
+        boards = _boards(grid.lo, grid.hi)
+        sets = [None, boards, boards[:2], boards[1:]]
+        ctx.server_start(slots=3, max_batch_rays=1 << 16)
+        rng = np.random.default_rng(4)
+        reqs = []
+        for i in range(18):
+            fi = int(rng.integers(0, len(frames)))
+            views = _random_request(rng, grid)
+            q = sets[int(rng.integers(0, len(sets)))]
+            st = st_a if rng.random() < 0.6 else st_u
+            reqs.append((ctx.submit(frames[fi][1], views, st, quads=q), fi, views, q, st))
+        _wait(ctx, [r[0] for r in reqs])
+        seen = set()
+        for t, fi, views, q, st in reqs:
+            got = to_np(ctx.request_outputs(t))
+            solo = to_np(ctx.trace_scene(frames[fi][1], views, np.zeros((0, 3, 3)) if q is None else q, st))
+            torch.cuda.synchronize()
+            for k in solo:
+                assert np.array_equal(got[k].view(np.uint8), solo[k].view(np.uint8)), (t, k)
+            seen.update(np.unique(got["surface"]).tolist())
+            ctx.request_release(t)
+        assert {0, 1, 2}.issubset(seen), seen
         ctx.server_stop()
     finally:
         ctx.close()
