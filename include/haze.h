@@ -433,6 +433,14 @@ hz_status hz_membench_gather(hz_ctx *ctx, const hz_grid *grid, int32_t voxel_byt
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of multi-view requests                   */
 /* ---------------------------------------------------------------------- */
+/* The paper defines no serving interface.  What it fixes is the use: every
+ * camera renders through the same time-varying 3D volume, so views of one
+ * frame are consistent by construction (Sec. 1; multi-view results, Sec. 4.2),
+ * at interactive frame rates (abstract; Sec. 4.1).  The request, batching,
+ * admission and release semantics below are this library's own design for
+ * that use: requests for fields of one grid and storage type are traced in
+ * shared launches, and each request's result is the one hz_trace_views gives
+ * for it alone. */
 
 typedef uint64_t hz_ticket;
 
