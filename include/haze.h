@@ -100,13 +100,10 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  * method and brick depth change only how delta_n is rounded (all meet the same
  * accuracy and each is bitwise repeatable):
  *   "march.refill_min"     refill a wave once this many of its 64 lanes are
- *                          idle, 1..64 (default 32)
+ *                          idle, 1..64 (default 64: whole batches, so a
+ *                          wave's lanes stay one pixel tile)
  *   "march.blocks_per_cu"  cap on resident 256-thread workgroups per CU,
  *                          0 = as many as fit (default 0)
- *   "march.thin"           1: with F32 fields and more rays than the resident
- *                          lanes, a third of the march's workgroups exit at
- *                          once (fewer gathers in flight); 0: all march
- *                          (default 1)
  *   "splat.method"         0 or 1: gather (one workgroup per 8x8xBZ voxel
  *                          brick, fixed FP32 summation order; the default), 2: scatter
  *                          (voxel tiles with 64-bit fixed-point accumulation in

@@ -176,7 +176,6 @@ struct TraceLaunch {
     TraceGrid grid;
     TraceStep step;
     int32_t refill_min;    // refill a wave once this many lanes are idle
-    int32_t thin;          // F32 fields with more rays than lanes: a third of the workgroups exit at once
     int32_t nquads;        // scene boards, tested before, inside and after the volume
     int32_t ninner;        // boards that may cross the volume: tested on every step
     uint32_t inner_idx;    // their indices, one byte each (lowest byte first)

@@ -55,7 +55,7 @@ typedef const gb_u32x4 __attribute__((address_space(1))) *gb_ptr;
 // per wave, longest rays first): the thread casts its pixel's pinhole ray
 // and walks straight through the grid box in steps of `step` metres from the
 // entry point, reading at every sample the 8 corners of its cell as the
-// marcher does (cell index clamped to [0, R-2]; the two x-neighbours of each
+// marcher does (cell index clamped to [0, R-2]; the two z-neighbours of each
 // of the 4 rows in one 16 or 32 byte stretch).  The words are folded into
 // one value per thread so no load can be dropped; the samples are counted
 // (one atomic per wave).
@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_gather_hits(const char *__restrict__ f,
         float t0 = 0.0f, t1 = 0.0f;
         const bool in = enter_volume(L.grid, J.eye, d, t0, &t1);
         const TraceGrid &G = L.grid;
-        const uint32_t row = (uint32_t)G.res[0], slab = (uint32_t)G.res[0] * (uint32_t)G.res[1];
+        // the packed field's layout: z fastest, then x, then y
+        const uint32_t row = (uint32_t)G.res[2], slab = (uint32_t)G.res[0] * (uint32_t)G.res[2];
         for (uint32_t s = 0; in; ++s) {
             const float t = fmaf((float)s, step, t0);
             if (!(t < t1)) break;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_gather_hits(const char *__restrict__ f,
                 const float u = fmaf(fmaf(t, d[a], J.eye[a]), G.inv_sp[a], G.off[a]);
                 i[a] = (uint32_t)__builtin_amdgcn_fmed3f(floorf(u), 0.0f, G.maxi[a]);
             }
-            const uint32_t b = (i[2] * slab + i[1] * row) + i[0];
+            const uint32_t b = (i[1] * slab + i[0] * row) + i[2];
             const uint32_t c[4] = {b, b + row, b + slab, b + slab + row};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {

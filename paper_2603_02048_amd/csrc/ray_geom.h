@@ -90,8 +90,12 @@ __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, 
     const int32_t within = local & 63;
     const int32_t ty = tile / J.tiles_x;
     r.job = lo;
-    r.p = (tile - ty * J.tiles_x) * 8 + (within & 7);
-    r.q = ty * 8 + (within >> 3);
+    // column-major inside the tile: consecutive slots (lanes) are vertically
+    // adjacent pixels, whose rays sit at nearly the same height; with z the
+    // field's fastest axis their gathers fall in the same cache lines, which
+    // the texture-address unit serves together
+    r.p = (tile - ty * J.tiles_x) * 8 + (within >> 3);
+    r.q = ty * 8 + (within & 7);
     r.out = r.q * J.width + r.p;
     return r.p < J.width && r.q < J.height;
 }

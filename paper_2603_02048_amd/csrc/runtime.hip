@@ -35,9 +35,10 @@ hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const flo
                                 const uint32_t *, hipStream_t, const KTimer &);
 int scatter_max_rows(const SplatParams &P);
 int scatter_rows_limit();
-hipError_t launch_grad_pack(int, const float *, const int32_t[3], const float[3], float, void *, hipStream_t,
+hipError_t launch_grad_pack(int, const float *, bool, const int32_t[3], const float[3], float, void *, hipStream_t,
                             const KTimer &);
-hipError_t launch_field_unpack(int, const void *, int64_t, float, float *, float *, float *, float *, hipStream_t);
+hipError_t launch_field_unpack(int, const void *, const int32_t[3], float, float *, float *, float *, float *,
+                               hipStream_t);
 hipError_t launch_raygen(const TraceLaunch &, bool, hipStream_t, const KTimer &);
 hipError_t launch_march(int, const TraceLaunch &, int, hipStream_t, const KTimer &);
 hipError_t launch_put_table(void *dst, const void *src, size_t bytes, hipStream_t s);
@@ -137,9 +138,8 @@ struct hz_ctx {
     int march_bpc[3] = {0, 0, 0};          // by dtype, no scene boards
     int march_bpc_scene[3][3] = {};      // by scene mode (outer boards / inner boards / mesh) and dtype
     // march tuning (hz_ctx_tune)
-    int32_t refill_min = 32;
+    int32_t refill_min = 64;
     int32_t blocks_per_cu = 0;   // 0: as many as fit
-    int32_t march_thin = 1;      // F32 with more rays than lanes: a third of the workgroups exit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8
     int32_t scan_fault_test = 0; // 1: the one-pass scan's waits give up (fault test)
@@ -617,9 +617,6 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
     if (k == "march.refill_min") {
         if (value < 1 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.refill_min must be in [1, 64]");
         c->refill_min = (int32_t)value;
-    } else if (k == "march.thin") {
-        if (value != 0 && value != 1) return fail(HZ_E_INVALID, "hz_ctx_tune: march.thin must be 0 or 1");
-        c->march_thin = (int32_t)value;
     } else if (k == "march.blocks_per_cu") {
         if (value < 0 || value > 64) return fail(HZ_E_INVALID, "hz_ctx_tune: march.blocks_per_cu must be in [0, 64]");
         c->blocks_per_cu = (int32_t)value;
@@ -774,13 +771,14 @@ static void register_field(hz_ctx *c, hz_field *f)
 // index field
 // ---------------------------------------------------------------------------
 
-static hz_status pack_field(hz_ctx *c, const float *dn, const hz_grid *g, hz_field *f, hipStream_t s)
+// dn_zfast: delta_n as the splat leaves it (z fastest); otherwise [z][y][x].
+static hz_status pack_field(hz_ctx *c, const float *dn, bool dn_zfast, const hz_grid *g, hz_field *f, hipStream_t s)
 {
     int32_t res[3] = {g->res[0], g->res[1], g->res[2]};
     float inv_sp[3];
     for (int a = 0; a < 3; ++a) inv_sp[a] = (float)((double)g->res[a] / (g->hi[a] - g->lo[a]));
     const KTimer t = prof_timer(c, "grad_pack");
-    HZ_HIP(launch_grad_pack((int)f->dtype, dn, res, inv_sp, f->store_scale, f->data, s, t), "grad/pack launch");
+    HZ_HIP(launch_grad_pack((int)f->dtype, dn, dn_zfast, res, inv_sp, f->store_scale, f->data, s, t), "grad/pack launch");
     prof_commit(c, "grad_pack", t);
     return HZ_OK;
 }
@@ -909,7 +907,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         field_destroy(f);
         return hip_fail(e, "splat launch");
     }
-    st = pack_field(c, (const float *)c->dn.ptr, g, f, s);
+    st = pack_field(c, (const float *)c->dn.ptr, true, g, f, s);
     if (st != HZ_OK) {
         field_destroy(f);
         return st;
@@ -943,7 +941,7 @@ extern "C" hz_status hz_index_field_from_grid(hz_ctx *c, const float *dn, const 
     hz_field *f = nullptr;
     st = new_field(c, g, dtype, store_scale, s, &f);
     if (st != HZ_OK) return st;
-    st = pack_field(c, dn, g, f, s);
+    st = pack_field(c, dn, false, g, f, s);
     CallMark done;
     if (st == HZ_OK) st = mark_issue(c, s, &done);
     if (st != HZ_OK) {
@@ -966,10 +964,10 @@ extern "C" hz_status hz_field_read(hz_ctx *c, const hz_field *fc, float *dn, flo
     if (st != HZ_OK) return st;
     HZ_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t nv = (int64_t)f->grid.res[0] * f->grid.res[1] * f->grid.res[2];
     st = field_order_read(c, f, s);
     if (st != HZ_OK) return st;
-    HZ_HIP(launch_field_unpack((int)f->dtype, f->data, nv, 1.0f / f->store_scale, dn, gx, gy, gz, s), "unpack launch");
+    HZ_HIP(launch_field_unpack((int)f->dtype, f->data, f->grid.res, 1.0f / f->store_scale, dn, gx, gy, gz, s),
+           "unpack launch");
     CallMark done;
     st = mark_issue(c, s, &done);
     if (st == HZ_OK) field_mark_used(f, done);
@@ -1268,7 +1266,6 @@ static hz_status prepare_trace(hz_ctx *c, const hz_field *fc, const hz_view *vie
     make_trace_grid(f->grid, f->store_scale, &L.grid);
     make_trace_step(*step, f->grid, &L.step);
     L.refill_min = c->refill_min;
-    L.thin = c->march_thin;
     L.inv_len_bin = length_bin_scale(f->grid);
     return HZ_OK;
 }

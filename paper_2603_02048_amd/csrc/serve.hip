@@ -275,8 +275,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     L.inv_len_bin = length_bin_scale(field_grid(head->field));
     make_trace_grid(field_grid(head->field), field_scale(head->field), &L.grid);
     make_trace_step(head->step, field_grid(head->field), &L.step);
-    L.refill_min = 32;
-    L.thin = 1;
+    L.refill_min = 64;
     const int dt = (int)field_dtype(head->field);
     const int blocks = (int)std::max<int64_t>(
         1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt, L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0)));

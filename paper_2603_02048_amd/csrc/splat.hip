@@ -490,7 +490,7 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
             float sum = acc[v];
 #pragma unroll
             for (int w = 0; w < SPLAT_WAVES - 1; ++w) sum += partial[w][v][lane];
-            if (vz0 + v < P.res[2]) dn[((int64_t)(vz0 + v) * P.res[1] + vy) * P.res[0] + vx] = sum * sc;
+            if (vz0 + v < P.res[2]) dn[((int64_t)vy * P.res[0] + vx) * P.res[2] + vz0 + v] = sum * sc;
         }
     }
 }
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_splat_scatter(SplatParams P, con
         for (int v = threadIdx.x; v < SC_TX * SC_TY * SC_TZ; v += SC_THREADS) {
             const int li = v % SC_TX, lj = (v / SC_TX) % SC_TY, lk = v / (SC_TX * SC_TY);
             if (li < nt[0] && lj < nt[1] && lk < nt[2])
-                dn[((int64_t)(o[2] + lk) * P.res[1] + (o[1] + lj)) * P.res[0] + (o[0] + li)] = __builtin_nanf("");
+                dn[((int64_t)(o[1] + lj) * P.res[0] + (o[0] + li)) * P.res[2] + (o[2] + lk)] = __builtin_nanf("");
         }
         return;
     }
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(SC_THREADS) void k_splat_scatter(SplatParams P, con
         const int li = v % SC_TX, lj = (v / SC_TX) % SC_TY, lk = v / (SC_TX * SC_TY);
         if (li < nt[0] && lj < nt[1] && lk < nt[2]) {
             const long long sum = (long long)acc[v];
-            dn[((int64_t)(o[2] + lk) * P.res[1] + (o[1] + lj)) * P.res[0] + (o[0] + li)] =
+            dn[((int64_t)(o[1] + lj) * P.res[0] + (o[0] + li)) * P.res[2] + (o[2] + lk)] =
                 (float)((double)sum * out_scale);
         }
     }
@@ -676,10 +676,12 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
-// A workgroup covers 64 x 4 columns of GP_Z voxels along z: grid
-// (ceil(rx/64), ceil(ry/4), ceil(rz/GP_Z)), so no index division.  Walking up
-// the column keeps the z-neighbours in registers (5 loads per voxel, not 7).
-constexpr int GP_Z = 4;
+// A workgroup covers 64 (z) x 4 (x) rows of GP_Y voxels along y: grid
+// (ceil(rz/64), ceil(rx/4), ceil(ry/GP_Y)), so no index division; lanes run
+// along z, the fastest axis of the packed field, so its stores coalesce.
+// Walking along y keeps the y-neighbours in registers (5 loads per voxel, not
+// 7).
+constexpr int GP_Y = 4;
 
 template <int DT>
 __device__ __forceinline__ void store_voxel(void *__restrict__ out, int32_t v, float c, float gx, float gy, float gz,
@@ -712,48 +714,63 @@ __device__ __forceinline__ float central(float fm, float c, float fp, int32_t id
     return (fp - fm) * (0.5f * inv);
 }
 
+// The packed field keeps z fastest: voxel (i, j, k) at (j rx + i) rz + k.  z
+// is the cameras' up axis (rays run across it): the 8 x 8 pixel tile a wave
+// marches spans a few voxels in z and in one horizontal axis, and with z
+// fastest its rows share cache lines whichever horizontal direction the view
+// looks along (with x fastest, views along x gathered from twice the lines).
+// delta_n is read with strides (dsx, dsy, dsz): z-fast from the splat,
+// [z][y][x] from hz_index_field_from_grid.
 template <int DT>
-__global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t rx, int32_t ry, int32_t rz,
-                                                   float ix, float iy, float iz, float scale, void *__restrict__ out)
+__global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t dsx, int32_t dsy,
+                                                   int32_t dsz, int32_t rx, int32_t ry, int32_t rz, float ix,
+                                                   float iy, float iz, float scale, void *__restrict__ out)
 {
-    const int32_t i = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
-    const int32_t j = (int32_t)blockIdx.y * 4 + (int32_t)(threadIdx.x >> 6);
-    const int32_t k0 = (int32_t)blockIdx.z * GP_Z;
-    if (i >= rx || j >= ry) return;
+    const int32_t k = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
+    const int32_t i = (int32_t)blockIdx.y * 4 + (int32_t)(threadIdx.x >> 6);
+    const int32_t j0 = (int32_t)blockIdx.z * GP_Y;
+    if (k >= rz || i >= rx) return;
     // voxel counts are below 2^31 (checked on the host): 32-bit index math
-    const int32_t sy = rx, sz = rx * ry;
-    int32_t v = (k0 * ry + j) * rx + i;
-    // x and y neighbours (and the z ones, from the column walk) stay inside
-    // the grid: a face uses the one-sided difference
-    const int32_t xm = i > 0 ? -1 : 0, xp = i < rx - 1 ? 1 : 0;
-    const int32_t ym = j > 0 ? -sy : 0, yp = j < ry - 1 ? sy : 0;
-    float zm = k0 > 0 ? dn[v - sz] : 0.0f;
-    float c = dn[v];
-    const int32_t k1 = min(k0 + GP_Z, rz);
-    for (int32_t k = k0; k < k1; ++k) {
-        const float zp = k + 1 < rz ? dn[v + sz] : 0.0f;
-        const float gx = central(dn[v + xm], c, dn[v + xp], i, rx, ix);
-        const float gy = central(dn[v + ym], c, dn[v + yp], j, ry, iy);
-        const float gz = central(zm, c, zp, k, rz, iz);
+    int32_t u = i * dsx + j0 * dsy + k * dsz;    // delta_n
+    int32_t v = (j0 * rx + i) * rz + k;          // packed voxel
+    const int32_t vy = rx * rz;
+    // x and z neighbours (and the y ones, from the walk) stay inside the
+    // grid: a face uses the one-sided difference
+    const int32_t xm = i > 0 ? -dsx : 0, xp = i < rx - 1 ? dsx : 0;
+    const int32_t zm = k > 0 ? -dsz : 0, zp = k < rz - 1 ? dsz : 0;
+    float ym = j0 > 0 ? dn[u - dsy] : 0.0f;
+    float c = dn[u];
+    const int32_t j1 = min(j0 + GP_Y, ry);
+    for (int32_t j = j0; j < j1; ++j) {
+        const float yp = j + 1 < ry ? dn[u + dsy] : 0.0f;
+        const float gx = central(dn[u + xm], c, dn[u + xp], i, rx, ix);
+        const float gy = central(ym, c, yp, j, ry, iy);
+        const float gz = central(dn[u + zm], c, dn[u + zp], k, rz, iz);
         store_voxel<DT>(out, v, c, gx, gy, gz, scale);
-        zm = c;
-        c = zp;
-        v += sz;
+        ym = c;
+        c = yp;
+        u += dsy;
+        v += vy;
     }
 }
 
+// Packed (z-fast) field -> [z][y][x] arrays: one thread per output voxel v.
 template <int DT>
-__global__ __launch_bounds__(256) void k_field_unpack(const void *__restrict__ in, int64_t nv, float inv_scale,
-                                                      float *__restrict__ dn, float *__restrict__ gx,
-                                                      float *__restrict__ gy, float *__restrict__ gz)
+__global__ __launch_bounds__(256) void k_field_unpack(const void *__restrict__ in, int32_t rx, int32_t ry,
+                                                      int32_t rz, float inv_scale, float *__restrict__ dn,
+                                                      float *__restrict__ gx, float *__restrict__ gy,
+                                                      float *__restrict__ gz)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv) return;
+    const int64_t nxy = (int64_t)rx * ry;
+    if (v >= nxy * rz) return;
+    const int64_t k = v / nxy, r = v - k * nxy;
+    const int64_t w = r * rz + k;   // r = j rx + i
     float4 f;
     if (DT == DT_F32) {
-        f = reinterpret_cast<const float4 *>(in)[v];
+        f = reinterpret_cast<const float4 *>(in)[w];
     } else {
-        const ushort4 h = reinterpret_cast<const ushort4 *>(in)[v];
+        const ushort4 h = reinterpret_cast<const ushort4 *>(in)[w];
         if (DT == DT_F16) {
             f = make_float4(__half2float(__ushort_as_half(h.x)), __half2float(__ushort_as_half(h.y)),
                             __half2float(__ushort_as_half(h.z)), __half2float(__ushort_as_half(h.w)));
@@ -859,33 +876,38 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
     return hipGetLastError();
 }
 
-hipError_t launch_grad_pack(int dtype, const float *dn, const int32_t res[3], const float inv_sp[3], float scale,
-                            void *out, hipStream_t s, const KTimer &t)
+// dn_zfast: delta_n as the splat writes it (z fastest: (j rx + i) rz + k);
+// otherwise [z][y][x].
+hipError_t launch_grad_pack(int dtype, const float *dn, bool dn_zfast, const int32_t res[3], const float inv_sp[3],
+                            float scale, void *out, hipStream_t s, const KTimer &t)
 {
-    const dim3 g((unsigned)((res[0] + 63) / 64), (unsigned)((res[1] + 3) / 4), (unsigned)((res[2] + GP_Z - 1) / GP_Z)),
+    const dim3 g((unsigned)((res[2] + 63) / 64), (unsigned)((res[0] + 3) / 4), (unsigned)((res[1] + GP_Y - 1) / GP_Y)),
         b(256);
+    const int32_t dsx = dn_zfast ? res[2] : 1, dsy = dn_zfast ? res[0] * res[2] : res[0],
+                  dsz = dn_zfast ? 1 : res[0] * res[1];
     if (dtype == DT_F32)
-        hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
-                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0], res[1],
+                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     else if (dtype == DT_F16)
-        hipExtLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
-                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0], res[1],
+                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     else
-        hipExtLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, t.start, t.stop, 0, dn, res[0], res[1], res[2],
-                              inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+        hipExtLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0],
+                              res[1], res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
     return hipGetLastError();
 }
 
-hipError_t launch_field_unpack(int dtype, const void *in, int64_t nv, float inv_scale, float *dn, float *gx,
+hipError_t launch_field_unpack(int dtype, const void *in, const int32_t res[3], float inv_scale, float *dn, float *gx,
                                float *gy, float *gz, hipStream_t s)
 {
-    const dim3 g(blocks_for(nv, 256)), b(256);
+    const dim3 g(blocks_for((int64_t)res[0] * res[1] * res[2], 256)), b(256);
     if (dtype == DT_F32)
-        hipLaunchKernelGGL(k_field_unpack<DT_F32>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+        hipLaunchKernelGGL(k_field_unpack<DT_F32>, g, b, 0, s, in, res[0], res[1], res[2], inv_scale, dn, gx, gy, gz);
     else if (dtype == DT_F16)
-        hipLaunchKernelGGL(k_field_unpack<DT_F16>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+        hipLaunchKernelGGL(k_field_unpack<DT_F16>, g, b, 0, s, in, res[0], res[1], res[2], inv_scale, dn, gx, gy, gz);
     else
-        hipLaunchKernelGGL(k_field_unpack<DT_BF16>, g, b, 0, s, in, nv, inv_scale, dn, gx, gy, gz);
+        hipLaunchKernelGGL(k_field_unpack<DT_BF16>, g, b, 0, s, in, res[0], res[1], res[2], inv_scale, dn, gx, gy,
+                           gz);
     return hipGetLastError();
 }
 

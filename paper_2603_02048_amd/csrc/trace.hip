@@ -18,11 +18,14 @@
 //             it also clears the counter set of the next launch
 //   k_raygen_place  places the entering rays in a hit list sorted by bin
 //             (wave ballots + mbcnt ranks, one atomic per workgroup and bin)
-//   k_march   persistent waves pull hit rays from the list; when enough lanes
-//             have finished, the idle lanes are refilled together (ballot of
-//             idle lanes, one atomic per wave, mbcnt rank), which keeps the
-//             wave busy despite the spread of step counts adaptive stepping
-//             causes; finished rays write their outputs at the next refill.
+//   k_march   persistent waves pull hit rays from the list in batches of
+//             64; once refill_min lanes have finished (by default all of
+//             them), the idle lanes are refilled together (ballot of idle
+//             lanes, one atomic per batch, mbcnt rank); finished rays write
+//             their outputs at the next refill.  The length sort keeps the
+//             lanes of a batch finishing together, and whole-batch refills
+//             keep a wave's lanes one 8x8 pixel tile, whose rays gather from
+//             few cache lines (see sample_field).
 //             Each ray's arithmetic is independent of which lane or wave runs
 //             it, so results are bitwise repeatable.
 //
@@ -494,7 +497,9 @@ __device__ __forceinline__ void wsum(float4 &v, float wgt, const float4 &c)
 }
 
 // Cell of x and the trilinear weights in it: cell index clamped to [0, R-2],
-// so the outer half-voxel extrapolates linearly.  (Fields hold fewer than
+// so the outer half-voxel extrapolates linearly; b is the index of the
+// cell's corner voxel in the packed field, whose fastest axis is z
+// (k_grad_pack).  (Fields hold fewer than
 // 2^31 voxels, checked on the host: 32-bit indices.  A NaN coordinate
 // converts to cell 0 and poisons the weights, which the march's finiteness
 // test catches.)
@@ -508,10 +513,10 @@ __device__ __forceinline__ void cell_of(const TraceGrid &G, const float x[3], ui
         i[a] = (uint32_t)fl;
         t[a] = u - fl;
     }
-    b = (i[2] * (uint32_t)G.res[1] + i[1]) * (uint32_t)G.res[0] + i[0];
+    b = (i[1] * (uint32_t)G.res[0] + i[0]) * (uint32_t)G.res[2] + i[2];
 }
 
-// F16/BF16 voxels are 8 bytes; the two x-neighbours of a cell row are one
+// F16/BF16 voxels are 8 bytes; the two z-neighbours of a cell row are one
 // 16-byte load (8-byte aligned, which the hardware serves as one dwordx4).
 typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 // The field pointer reaches the kernel through the job table, so the compiler
@@ -541,44 +546,55 @@ __device__ __forceinline__ float4 half4_to_float4(uint32_t lo, uint32_t hi)
 }
 
 template <int DT>
-__device__ __forceinline__ void load_xpair_at(gpair_ptr p, float4 &a, float4 &b)
+__device__ __forceinline__ void load_pair_at(gpair_ptr p, float4 &a, float4 &b)
 {
     const u32x4_a8 v = *p;
     a = half4_to_float4<DT>(v.x, v.y);
     b = half4_to_float4<DT>(v.z, v.w);
 }
 
+// Trilinear sample of (delta_n, grad n) at x (Sec. 3.3.1): 8 corners, 4 row
+// loads of a z-neighbour pair each.  The gathers are bound by how the
+// texture-address unit serves a wave's 64 addresses: lanes next to each other
+// that fall in one cache line are served together.  The packed field keeps z
+// (the cameras' up axis) fastest and the queue orders a tile's pixels
+// column-major, so neighbouring lanes are vertically adjacent pixels whose
+// rows share lines whatever horizontal direction the view looks along.  (With
+// x fastest and row-major tiles only views along y coalesced: single 1280x720
+// views along x took 1.8x as long.)
 template <int DT>
 __device__ __forceinline__ float4 sample_field(const TraceGrid &G, const void *__restrict__ f, const float x[3])
 {
     uint32_t b;
     float t[3];
     cell_of(G, x, b, t);
-    const uint32_t sy = (uint32_t)G.res[0], sz = (uint32_t)G.res[0] * (uint32_t)G.res[1];
+    const uint32_t sx = (uint32_t)G.res[2], sy = (uint32_t)G.res[0] * (uint32_t)G.res[2];
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
-    // Addresses by 64-bit pointer steps from the corner voxel: the x-neighbour
-    // is the load's immediate offset, and the y and z rows one add each
-    // (instead of a 32-bit index and a 64-bit address per load).
+    // Addresses by 64-bit pointer steps from the corner voxel: the
+    // z-neighbour is the load's immediate offset, and the x and y rows one add
+    // each (instead of a 32-bit index and a 64-bit address per load).  The
+    // corners keep their names whatever the layout, so the weighted sum below
+    // runs in the same order.
     if (DT == DT_F32) {
-        const gfloat4_ptr p0 = (gfloat4_ptr)f + b, p1 = p0 + sz;
-        const gfloat4_ptr q0 = p0 + sy, q1 = p1 + sy;
+        const gfloat4_ptr p0 = (gfloat4_ptr)f + b, p1 = p0 + sy;
+        const gfloat4_ptr q0 = p0 + sx, q1 = p1 + sx;
         c000 = load_f32x4(p0, 0);
-        c100 = load_f32x4(p0, 1);
-        c010 = load_f32x4(q0, 0);
-        c110 = load_f32x4(q0, 1);
-        c001 = load_f32x4(p1, 0);
-        c101 = load_f32x4(p1, 1);
-        c011 = load_f32x4(q1, 0);
+        c001 = load_f32x4(p0, 1);
+        c100 = load_f32x4(q0, 0);
+        c101 = load_f32x4(q0, 1);
+        c010 = load_f32x4(p1, 0);
+        c011 = load_f32x4(p1, 1);
+        c110 = load_f32x4(q1, 0);
         c111 = load_f32x4(q1, 1);
     } else {
         const gpair_ptr p0 = (gpair_ptr)(reinterpret_cast<const uint16_t *>(f) + 4 * (size_t)b);
-        const gpair_ptr p1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sz);
-        const gpair_ptr q0 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sy);
-        const gpair_ptr q1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p1 + 4 * (size_t)sy);
-        load_xpair_at<DT>(p0, c000, c100);
-        load_xpair_at<DT>(q0, c010, c110);
-        load_xpair_at<DT>(p1, c001, c101);
-        load_xpair_at<DT>(q1, c011, c111);
+        const gpair_ptr p1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sy);
+        const gpair_ptr q0 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p0 + 4 * (size_t)sx);
+        const gpair_ptr q1 = (gpair_ptr)((const uint16_t __attribute__((address_space(1))) *)p1 + 4 * (size_t)sx);
+        load_pair_at<DT>(p0, c000, c001);
+        load_pair_at<DT>(q0, c100, c101);
+        load_pair_at<DT>(p1, c010, c011);
+        load_pair_at<DT>(q1, c110, c111);
     }
     // trilinear weights, then one FMA per corner and channel
     const float ux = 1.0f - t[0], uy = 1.0f - t[1], uz = 1.0f - t[2];
@@ -634,19 +650,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
     // counter past the static range, fetched one batch ahead (the atomic's
     // latency hides behind the march).  Each wave keeps its reserve
     // [next, end) of hit indices.
-    // With F32 samples (128 B per step) and more rays than the resident waves
-    // hold (so lanes are refilled anyway), two thirds of the waves march
-    // faster than all of them (fewer gathers in flight per CU: 4 instead of 6
-    // waves per SIMD, ~5% less time on 8 views of 1280x720).  Every third
-    // workgroup then exits at once, which leaves each CU two thirds of its
-    // workgroups however they were placed, and the rest are renumbered
-    // densely.  With fewer rays, every wave keeps its static batch.
-    uint32_t blk = blockIdx.x, nblk = gridDim.x;
-    if (DT == DT_F32 && SCENE != 2 && L.thin && ((nh + 63u) >> 6) > nblk * (blockDim.x >> 6)) {
-        if (blk % 3u == 2u) return;
-        blk = 2u * (blk / 3u) + blk % 3u;
-        nblk = 2u * (nblk / 3u) + min(nblk % 3u, 2u);
-    }
+    const uint32_t blk = blockIdx.x, nblk = gridDim.x;
     const uint32_t nwaves = nblk * (blockDim.x >> 6);
     const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blk * (blockDim.x >> 6) + (threadIdx.x >> 6));
     const uint32_t sb = 64u;
