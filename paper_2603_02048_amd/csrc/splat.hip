@@ -381,7 +381,7 @@ __device__ __forceinline__ void splat_row_from(int v0, const SplatParams &P, flo
 // dispatcher balances bricks of unequal cost.  Workgroups are remapped so
 // that each XCD (workgroups are dealt round-robin over the 8 XCDs) walks a
 // contiguous run of bricks and keeps its particle rows in its own L2.
-// waves per brick (4: 0.565 ms at config 2; 8: 0.621 ms; 1: 0.649 ms)
+// waves per brick (262,144 particles on a 128^3 grid: 4 waves 0.565 ms; 8: 0.621 ms; 1: 0.649 ms)
 constexpr int SPLAT_WAVES = 4;
 
 template <int BZ>

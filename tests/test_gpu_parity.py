@@ -338,6 +338,23 @@ def test_grid_axis_at_limit(ctx, haze):
         field.release()
 
 
+def test_field_from_grid_round_trip(ctx, haze):
+    # the packed field keeps its own voxel order; the [z][y][x] export must
+    # give back the [z][y][x] input bit for bit (F32), and the gradient the
+    # central / one-sided differences of it, voxel by voxel, on a ragged grid
+    grid = W.make_grid((0.0, 0.0, 0.0), (1.0, 0.8, 1.3), (7, 5, 11))
+    print("case field round trip: 7 x 5 x 11 grid, random delta-n", flush=True)
+    rng = np.random.default_rng(3)
+    dn = rng.standard_normal((11, 5, 7)).astype(np.float32) * np.float32(1e-4)
+    f = ctx.index_field_from_grid(torch.from_numpy(dn).cuda(), grid)
+    d, gx, gy, gz = _field_np(ctx, f)
+    assert np.array_equal(d.view(np.uint32), dn.view(np.uint32))
+    ref = np.gradient(dn.astype(np.float64), *[float(s) for s in grid.spacing[::-1]], edge_order=1)
+    for g, r, name in ((gz, ref[0], "z"), (gy, ref[1], "y"), (gx, ref[2], "x")):
+        assert np.abs(g - r).max() <= 1e-5 * np.abs(r).max(), name
+    f.release()
+
+
 def test_field_from_grid_linear_and_catenary(ctx, haze):
     # a linear delta-n grid: the GPU gradient is exact up to rounding and the
     # rays follow the oracle's (grid-exact) catenary replica
