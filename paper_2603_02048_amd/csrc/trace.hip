@@ -388,7 +388,14 @@ __device__ __forceinline__ uint32_t bin_rank(int bin, uint32_t (*wcnt)[kRayBins]
 template <int SCENE>
 __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
 {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // A tile's slots run down its columns (decode_slot), but the rays that
+    // miss write their outputs here, by pixel: the 64 threads of a tile take
+    // its slots transposed, so neighbouring threads write neighbouring pixels
+    // of a row.  (Which thread takes a slot changes nothing else: the counts
+    // are per workgroup, and the hit list is placed in slot order.)
+    const int l = (int)(threadIdx.x & 63);
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u) +
+                         (L.subset ? l : (((l & 7) << 3) | (l >> 3)));
     bool enters = false;
     int bin = 255;
     if (slot < L.nslots) {
