@@ -66,10 +66,7 @@ struct Request {
 
 // A device block held by the server for reuse (request outputs) or to be
 // freed with the lock dropped.
-struct Block {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
+using Block = PoolBlock;
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -102,8 +99,7 @@ struct Server {
     hz_ticket next_id = 1;
     hz_status fatal = HZ_OK;
     hipEvent_t t_ref = nullptr;        // device time origin of the batch timestamps
-    std::vector<Block> out_pool;       // released request outputs, by size class
-    uint64_t out_pool_bytes = 0;
+    OutputPool out_pool;               // released request outputs, by size class
     std::vector<Block> to_free;        // device blocks the scheduler frees unlocked
     std::vector<void *> to_free_host;  // pinned host blocks likewise
     size_t trim_fields = 0;            // bytes of pooled (released) field memory to give back, unlocked
@@ -143,25 +139,11 @@ static BatchKey make_key(const hz_field *f, const hz_step &st, const std::vector
     return k;
 }
 
-// Output blocks come in size classes, four per octave from 64 KiB, so that a
-// released block serves later requests of similar size.
-static size_t out_class(int64_t bytes)
-{
-    size_t p = (size_t)64 << 10;
-    while (p * 2 <= (size_t)bytes) p <<= 1;
-    for (size_t k = 0; k <= 4; ++k)
-        if ((size_t)bytes <= p + k * (p / 4)) return p + k * (p / 4);
-    return 2 * p;
-}
-
 // Return a request's outputs to the pool (its batch has completed; the caller
 // has finished reading them).  Called with the server lock held.
 static void pool_outputs(Server *S, Request *r)
 {
-    if (r->out_mem) {
-        S->out_pool.push_back({r->out_mem, r->out_cap});
-        S->out_pool_bytes += r->out_cap;
-    }
+    if (r->out_mem) S->out_pool.put(r->out_mem, r->out_cap);
     r->out_mem = nullptr;
     r->out_cap = 0;
 }
@@ -172,15 +154,7 @@ static void pool_outputs(Server *S, Request *r)
 static hz_status alloc_outputs(Server *S, Request *r)
 {
     const size_t cls = out_class(r->out_bytes);
-    r->out_mem = nullptr;
-    for (size_t i = 0; i < S->out_pool.size(); ++i)
-        if (S->out_pool[i].bytes == cls) {
-            r->out_mem = S->out_pool[i].ptr;
-            S->out_pool_bytes -= cls;
-            S->out_pool[i] = S->out_pool.back();
-            S->out_pool.pop_back();
-            break;
-        }
+    r->out_mem = S->out_pool.take(cls);
     if (!r->out_mem) {
         hz_status st = ctx_alloc_nowait(S->ctx, &r->out_mem, cls);
         if (st != HZ_OK) return st;
@@ -357,7 +331,7 @@ static void scheduler(Server *S)
             // pooled output blocks count as free memory: they are reused, or
             // given back when an allocation finds the budget short
             const std::vector<size_t> pick =
-                plan_batch(info, S->slot_capacity, (int64_t)(ctx_mem_avail(S->ctx) + S->out_pool_bytes), 256);
+                plan_batch(info, S->slot_capacity, (int64_t)(ctx_mem_avail(S->ctx) + S->out_pool.bytes), 256);
             if (pick.empty()) {
                 // the oldest request waits for memory; when stopping with nothing
                 // running, no memory will come back: fail what is left
@@ -385,9 +359,8 @@ static void scheduler(Server *S)
                 // pooled output blocks of other sizes, or released fields,
                 // hold the budget: give them back (below, unlocked); the rest
                 // waits for the next round
-                S->to_free.insert(S->to_free.end(), S->out_pool.begin(), S->out_pool.end());
-                S->out_pool.clear();
-                S->out_pool_bytes = 0;
+                const std::vector<Block> held = S->out_pool.drain();
+                S->to_free.insert(S->to_free.end(), held.begin(), held.end());
                 S->trim_fields = (size_t)out_class(S->pending[pick[batch.size()]]->out_bytes);
                 progressed = progressed || !S->to_free.empty();
             }
@@ -440,7 +413,7 @@ void server_destroy(Server *S)
         pool_outputs(S, kv.second);
         delete kv.second;
     }
-    for (const Block &b : S->out_pool) ctx_free(S->ctx, b.ptr, b.bytes);
+    for (const Block &b : S->out_pool.drain()) ctx_free(S->ctx, b.ptr, b.bytes);
     for (const Block &b : S->to_free) ctx_free(S->ctx, b.ptr, b.bytes);
     for (void *h : S->to_free_host) (void)hipHostFree(h);
     if (S->t_ref) (void)hipEventDestroy(S->t_ref);

@@ -81,4 +81,60 @@ inline int64_t view_slots(int32_t width, int32_t height)
 // exit_dir (3 f32), steps (u32), status (u8), surface (u8).
 constexpr int64_t kOutBytesPerRay = 8 + 12 + 12 + 4 + 1 + 1;
 
+// Request outputs come in size classes, four per octave from 64 KiB, so that
+// a released block serves later requests of similar size: the class of a
+// request of b bytes is the smallest p (1 + k/4), k = 0..4, p a power of two
+// from 64 KiB with p <= b (64 KiB for smaller b), that holds b; at most 1.25 b
+// above 64 KiB.
+inline size_t out_class(int64_t bytes)
+{
+    size_t p = (size_t)64 << 10;
+    while (p * 2 <= (size_t)bytes) p <<= 1;
+    for (size_t k = 0; k <= 4; ++k)
+        if ((size_t)bytes <= p + k * (p / 4)) return p + k * (p / 4);
+    return 2 * p;
+}
+
+// A device block (pointer and bytes) the serving loop holds.
+struct PoolBlock {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// Released request outputs kept for reuse, keyed by size class.  Host
+// bookkeeping only: the serving loop puts a block back once the request's
+// batch has completed and its outputs have been released, so a block taken
+// out is free on the device.
+struct OutputPool {
+    std::vector<PoolBlock> blocks;
+    uint64_t bytes = 0;   // total held
+
+    void put(void *ptr, size_t cls)
+    {
+        blocks.push_back({ptr, cls});
+        bytes += cls;
+    }
+    // A held block of class `cls`, or nullptr.
+    void *take(size_t cls)
+    {
+        for (size_t i = 0; i < blocks.size(); ++i)
+            if (blocks[i].bytes == cls) {
+                void *p = blocks[i].ptr;
+                bytes -= cls;
+                blocks[i] = blocks.back();
+                blocks.pop_back();
+                return p;
+            }
+        return nullptr;
+    }
+    // Everything held (to be freed), leaving the pool empty.
+    std::vector<PoolBlock> drain()
+    {
+        std::vector<PoolBlock> all;
+        all.swap(blocks);
+        bytes = 0;
+        return all;
+    }
+};
+
 }  // namespace haze

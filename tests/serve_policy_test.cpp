@@ -80,6 +80,52 @@ int main()
     CHECK(view_slots(1280, 720) == 1280 * 720);
     CHECK(view_slots(37, 23) == 5 * 3 * 64);
     CHECK(kOutBytesPerRay == 38);   // disp, exit_pos, exit_dir, steps, status, surface
+    // output size classes: hold the request, at least 64 KiB, at most 1.25x above that, monotone, four per octave
+    {
+        size_t prev = 0;
+        int classes_in_octave = 0;
+        size_t octave = (size_t)64 << 10;
+        for (int64_t b = 1; b <= ((int64_t)1 << 33); b = b < 4096 ? b + 1 : b + b / 97 + 1) {
+            const size_t c = out_class(b);
+            CHECK(c >= (size_t)b);
+            CHECK(c >= ((size_t)64 << 10));
+            if (b > ((int64_t)64 << 10)) CHECK((double)c <= 1.25 * (double)b);
+            CHECK(c >= prev);
+            if (c != prev) {
+                while (c > 2 * octave) {
+                    octave *= 2;
+                    classes_in_octave = 0;
+                }
+                CHECK(++classes_in_octave <= 4 + 1);
+            }
+            prev = c;
+        }
+        CHECK(out_class(0) == ((size_t)64 << 10));
+        CHECK(out_class((int64_t)64 << 10) == ((size_t)64 << 10));
+        CHECK(out_class(((int64_t)64 << 10) + 1) == ((size_t)80 << 10));
+        CHECK(out_class((int64_t)1 << 20) == ((size_t)1 << 20));
+        CHECK(out_class(((int64_t)1 << 20) + 1) == ((size_t)1280 << 10));
+    }
+    // the output pool: blocks come back by class, the byte count follows, drain empties it
+    {
+        OutputPool pool;
+        int a = 0, b = 0, c = 0;
+        pool.put(&a, 1024);
+        pool.put(&b, 2048);
+        pool.put(&c, 1024);
+        CHECK(pool.bytes == 4096);
+        CHECK(pool.take(4096) == nullptr);
+        void *x = pool.take(2048);
+        CHECK(x == &b && pool.bytes == 2048);
+        void *y = pool.take(1024), *z = pool.take(1024);
+        CHECK(((y == &a && z == &c) || (y == &c && z == &a)) && pool.bytes == 0);
+        CHECK(pool.take(1024) == nullptr);
+        pool.put(&a, 1024);
+        pool.put(&b, 4096);
+        const std::vector<PoolBlock> all = pool.drain();
+        CHECK(all.size() == 2 && pool.bytes == 0 && pool.blocks.empty());
+        CHECK(pool.take(4096) == nullptr);
+    }
     std::printf("%s (%d failures)\n", failures ? "FAILED" : "OK", failures);
     return failures ? 1 : 0;
 }
