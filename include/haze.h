@@ -466,6 +466,15 @@ hz_status hz_submit(hz_ctx *ctx, const hz_field *field, const hz_view *views, in
 hz_status hz_submit_scene(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
                           const hz_scene *scene, const hz_step *step, hz_ticket *out);
 
+/* hz_submit with a triangle mesh (as hz_trace_mesh, without tri_tests; the
+ * request's surface array reports the mesh surfaces).  `mesh` must stay alive
+ * until the request completes.  Only requests with the same mesh (and grid,
+ * storage type and step control) share a launch.  Errors: as hz_submit, and
+ * HZ_E_INVALID for a NULL mesh, a mesh of another context, or steps longer
+ * than the mesh's reach. */
+hz_status hz_submit_mesh(hz_ctx *ctx, const hz_field *field, const hz_view *views, int32_t nviews,
+                         const hz_mesh *mesh, const hz_step *step, hz_ticket *out);
+
 /* Poll a request: HZ_PENDING until its results are complete on the device,
  * then HZ_OK with *latency_s = seconds from submit to completion (may be
  * NULL).  Errors: HZ_E_NOTFOUND (unknown or already released ticket),

@@ -28,7 +28,12 @@ hz_status field_ready(hz_field *f, hipStream_t s);       // order a read on s af
 void field_use(hz_field *f, const CallMark &t);            // a read by the call with mark t
 hz_status ctx_mark(hz_ctx *c, hipStream_t s, CallMark *out);
 hz_status ctx_mark_sync(hz_ctx *c, const CallMark &t);    // block the host until the call's work is done
-int march_blocks(hz_ctx *c, int dt, int scene_mode);   // persistent march grid (scene mode 0, 1 or 2)
+int march_blocks(hz_ctx *c, int dt, int scene_mode);   // persistent march grid (scene mode 0, 1, 2 or 3)
+// mesh accessors implemented in mesh.hip
+const MeshLaunch &mesh_launch(const hz_mesh *m);
+float mesh_reach(const hz_mesh *m);
+hz_ctx *mesh_ctx(const hz_mesh *m);
+void mesh_use(hz_mesh *m, const CallMark &t);   // a read by the call with mark t
 void profile_add(hz_ctx *c, const char *name, double ms);
 hz_status set_error(hz_status s, const char *msg);
 hz_status field_usable(hz_ctx *c, const hz_field *f, const char *fn);   // pending device faults, bad fields

@@ -51,6 +51,7 @@ struct Request {
     hz_field *field = nullptr;
     std::vector<hz_view> views;
     std::vector<hz_quad> quads;   // scene boards (none: the backdrop only)
+    hz_mesh *mesh = nullptr;      // or a triangle-mesh scene
     hz_step step{};
     BatchKey key = zero_key();
     int64_t nrays = 0, nslots = 0, out_bytes = 0;
@@ -110,7 +111,7 @@ static double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-static BatchKey make_key(const hz_field *f, const hz_step &st, const std::vector<hz_quad> &quads)
+static BatchKey make_key(const hz_field *f, const hz_step &st, const std::vector<hz_quad> &quads, const hz_mesh *mesh)
 {
     BatchKey k = zero_key();
     const hz_grid &g = field_grid(f);
@@ -130,6 +131,7 @@ static BatchKey make_key(const hz_field *f, const hz_step &st, const std::vector
     k.max_steps = st.max_steps;
     k.tau_term = st.tau_term;
     k.nquads = (int32_t)quads.size();
+    k.mesh = (uint64_t)(uintptr_t)mesh;
     for (size_t q = 0; q < quads.size(); ++q)
         for (int a = 0; a < 3; ++a) {
             k.quads[q][a] = quads[q].origin[a];
@@ -195,7 +197,8 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
             local_ray += nr;
         }
     }
-    // the batch's boards (all its requests share them: same key) after the views
+    // the batch's boards (all its requests share them: same key) after the
+    // views, or its mesh
     Request *head = batch[0];
     TraceLaunch L{};
     std::vector<SceneQuad> qs;
@@ -204,6 +207,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
         hz_status st = build_scene(&sc, field_grid(head->field), &L, qs, "serve");
         if (st != HZ_OK) return st;
     }
+    if (head->mesh) L.mesh = mesh_launch(head->mesh);
     const size_t view_bytes = sizeof(TraceJob) * jobs.size();
     const size_t job_bytes = view_bytes + sizeof(SceneQuad) * qs.size();
     if (sl.jobs_cap < job_bytes) {
@@ -251,8 +255,8 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
     make_trace_step(head->step, field_grid(head->field), &L.step);
     L.refill_min = 64;
     const int dt = (int)field_dtype(head->field);
-    const int blocks = (int)std::max<int64_t>(
-        1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt, L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0)));
+    const int mode = L.mesh.ntris > 0 ? 3 : L.ninner > 0 ? 2 : L.nquads > 0 ? 1 : 0;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((slot + 255) / 256, march_blocks(S->ctx, dt, mode)));
     const bool clear = !sl.counters_clean;
     sl.counters_clean = false;
     // the dispatch packets of the first and last kernel record the batch's
@@ -270,6 +274,7 @@ static hz_status launch_batch(Server *S, Slot &sl, std::vector<Request *> &batch
         field_use(r->field, done);
         r->state = REQ_RUNNING;
     }
+    if (head->mesh) mesh_use(head->mesh, done);
     sl.reqs = batch;
     sl.busy = true;
     return HZ_OK;
@@ -472,7 +477,8 @@ extern "C" hz_status hz_server_stop(hz_ctx *c)
 }
 
 static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
-                             const hz_scene *scene, const hz_step *step, hz_ticket *out, const char *fn)
+                             const hz_scene *scene, const hz_mesh *mesh, const hz_step *step, hz_ticket *out,
+                             const char *fn)
 {
     if (!c || !f || !views || !out) return set_error(HZ_E_INVALID, "hz_submit: NULL argument");
     Server *S = ctx_server(c);
@@ -483,6 +489,12 @@ static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views,
     if (st != HZ_OK) return st;
     st = field_usable(c, f, fn);
     if (st != HZ_OK) return st;
+    if (mesh) {   // checked now, not at launch
+        if (mesh_ctx(mesh) != c) return set_error(HZ_E_INVALID, "hz_submit_mesh: mesh belongs to another context");
+        const float longest = step->uniform ? step->ds_uniform : step->ds_max;
+        if (longest > mesh_reach(mesh))
+            return set_error(HZ_E_INVALID, "hz_submit_mesh: the step is longer than the mesh's shell serves");
+    }
     if (scene && scene->nquads > 0) {   // the boards are checked now, not at launch
         TraceLaunch probe{};
         std::vector<SceneQuad> qs;
@@ -493,6 +505,7 @@ static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views,
     r->field = const_cast<hz_field *>(f);
     r->views.assign(views, views + nviews);
     if (scene && scene->nquads > 0) r->quads.assign(scene->quads, scene->quads + scene->nquads);
+    r->mesh = const_cast<hz_mesh *>(mesh);
     r->step = *step;
     for (int i = 0; i < nviews; ++i) {
         TraceJob J;
@@ -505,7 +518,7 @@ static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views,
         r->nslots += view_slots(views[i].width, views[i].height);
     }
     r->out_bytes = r->nrays * kOutBytesPerRay;
-    r->key = make_key(f, *step, r->quads);
+    r->key = make_key(f, *step, r->quads, r->mesh);
     uint64_t budget = 0;
     hz_ctx_memory(c, nullptr, &budget);
     if (r->nslots > S->slot_capacity || (uint64_t)out_class(r->out_bytes) > budget) {
@@ -527,13 +540,20 @@ static hz_status submit_impl(hz_ctx *c, const hz_field *f, const hz_view *views,
 extern "C" hz_status hz_submit(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
                                const hz_step *step, hz_ticket *out)
 {
-    return submit_impl(c, f, views, nviews, nullptr, step, out, "hz_submit");
+    return submit_impl(c, f, views, nviews, nullptr, nullptr, step, out, "hz_submit");
 }
 
 extern "C" hz_status hz_submit_scene(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
                                      const hz_scene *scene, const hz_step *step, hz_ticket *out)
 {
-    return submit_impl(c, f, views, nviews, scene, step, out, "hz_submit_scene");
+    return submit_impl(c, f, views, nviews, scene, nullptr, step, out, "hz_submit_scene");
+}
+
+extern "C" hz_status hz_submit_mesh(hz_ctx *c, const hz_field *f, const hz_view *views, int32_t nviews,
+                                    const hz_mesh *mesh, const hz_step *step, hz_ticket *out)
+{
+    if (!mesh) return set_error(HZ_E_INVALID, "hz_submit_mesh: mesh is NULL");
+    return submit_impl(c, f, views, nviews, nullptr, mesh, step, out, "hz_submit_mesh");
 }
 
 extern "C" hz_status hz_poll(hz_ctx *c, hz_ticket t, double *latency_s)

@@ -10,7 +10,8 @@ namespace haze {
 
 // What decides whether two requests can share one launch: the tracer's
 // launch-uniform data (grid geometry, storage type and scale, step control,
-// scene boards: each as origin, edge_u, edge_v).
+// scene boards: each as origin, edge_u, edge_v; the triangle mesh, by
+// identity).
 constexpr int kKeyQuads = 8;
 struct BatchKey {
     double lo[3], hi[3];
@@ -22,6 +23,7 @@ struct BatchKey {
     int32_t max_steps;
     float tau_term;
     int32_t nquads;
+    uint64_t mesh;   // the mesh scene's handle, 0 for none
     float quads[kKeyQuads][9];
 };
 

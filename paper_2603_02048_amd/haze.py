@@ -86,7 +86,7 @@ EXPORTS = ["hz_ctx_create", "hz_ctx_destroy", "hz_last_error", "hz_ctx_memory", 
            "hz_index_field_from_grid", "hz_field_read", "hz_field_info", "hz_field_release", "hz_trace_views",
            "hz_trace_views_noalloc", "hz_trace_scene", "hz_mesh_create", "hz_mesh_info", "hz_mesh_release",
            "hz_trace_mesh",
-           "hz_server_start", "hz_submit", "hz_submit_scene", "hz_poll", "hz_request_outputs",
+           "hz_server_start", "hz_submit", "hz_submit_scene", "hz_submit_mesh", "hz_poll", "hz_request_outputs",
            "hz_request_surface", "hz_request_timing", "hz_request_release", "hz_server_stop"]
 
 _lib = None
@@ -149,6 +149,9 @@ def lib():
         L.hz_submit_scene.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, C.POINTER(hz_scene), C.POINTER(hz_step),
                                       C.POINTER(C.c_uint64)]
         L.hz_submit_scene.restype = S
+        L.hz_submit_mesh.argtypes = [P, P, C.POINTER(hz_view), C.c_int32, P, C.POINTER(hz_step),
+                                     C.POINTER(C.c_uint64)]
+        L.hz_submit_mesh.restype = S
         L.hz_request_surface.argtypes = [P, C.c_uint64, C.POINTER(C.c_void_p)]
         L.hz_request_surface.restype = S
         L.hz_poll.argtypes, L.hz_poll.restype = [P, C.c_uint64, C.POINTER(C.c_double)], S
@@ -467,10 +470,17 @@ class Context:
     def server_start(self, slots: int = 4, max_batch_rays: int = 1 << 23):
         _check(lib().hz_server_start(C.c_void_p(self.handle), int(slots), int(max_batch_rays)), "server_start")
 
-    def submit(self, field: Field, views: Sequence, step, quads=None) -> int:
-        """Submit a request (with scene boards `quads`, (K, 3, 3), if given)."""
+    def submit(self, field: Field, views: Sequence, step, quads=None, mesh: Optional[Mesh] = None) -> int:
+        """Submit a request (with scene boards `quads`, (K, 3, 3), or a Mesh,
+        if given; the mesh must stay alive until the request completes)."""
         t = C.c_uint64()
-        if quads is None:
+        if mesh is not None:
+            if quads is not None:
+                raise ValueError("submit: boards and a mesh cannot be combined")
+            _check(lib().hz_submit_mesh(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views),
+                                        len(views), C.c_void_p(mesh.handle), C.byref(make_step(step)), C.byref(t)),
+                   "submit_mesh")
+        elif quads is None:
             _check(lib().hz_submit(C.c_void_p(self.handle), C.c_void_p(field.handle), make_views(views), len(views),
                                    C.byref(make_step(step)), C.byref(t)), "submit")
         else:

@@ -74,6 +74,15 @@ int main()
         auto p2 = plan_batch(r, 100, 1000, 8);
         CHECK(p2.size() == 2);
     }
+    // requests with different meshes never share a launch; the same mesh does
+    {
+        std::vector<PendingInfo> q = {req(1, 10, 10), req(1, 10, 10), req(1, 10, 10), req(1, 10, 10)};
+        q[0].key.mesh = 0x1000;
+        q[1].key.mesh = 0x2000;
+        q[2].key.mesh = 0x1000;
+        auto p = plan_batch(q, 100, 1000, 8);
+        CHECK(p.size() == 2 && p[0] == 0 && p[1] == 2);
+    }
     // slot counting: 8x8 tiles of 64 slots, ragged edges padded
     CHECK(view_slots(8, 8) == 64);
     CHECK(view_slots(9, 8) == 128);

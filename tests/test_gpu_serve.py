@@ -218,3 +218,76 @@ def test_serve_scene_boards_mix_equals_solo(haze):
         ctx.server_stop()
     finally:
         ctx.close()
+
+
+def test_serve_mesh_mix_equals_solo(haze):
+    """Requests against two triangle meshes (hz_submit_mesh) and without a
+    scene, interleaved: each result bitwise equal to a solo hz_trace_mesh
+    (or hz_trace_views) of the same views; the meshes' surfaces are met."""
+    from tests.test_gpu_scene import _boards
+    print("case serve meshes: 18 requests, two meshes and none", flush=True)
+    ctx = haze.Context(0)
+    try:
+        frames = _frames(ctx, haze, n=2)
+        grid = frames[0][0].grid
+        st_a, st_u = W.make_steps(grid)
+        reach = max(st_a.ds_max, st_u.ds_uniform)
+        boards = _boards(grid.lo, grid.hi)
+        meshes = [None, ctx.mesh_create(*W.tessellate_quads(boards, 4), reach=reach),
+                  ctx.mesh_create(*W.tessellate_quads(boards[1:], 3), reach=reach)]
+        ctx.server_start(slots=3, max_batch_rays=1 << 16)
+        rng = np.random.default_rng(6)
+        reqs = []
+        for i in range(18):
+            fi = int(rng.integers(0, len(frames)))
+            views = _random_request(rng, grid)
+            m = meshes[int(rng.integers(0, len(meshes)))]
+            st = st_a if rng.random() < 0.6 else st_u
+            reqs.append((ctx.submit(frames[fi][1], views, st, mesh=m), fi, views, m, st))
+        _wait(ctx, [r[0] for r in reqs])
+        seen = set()
+        for t, fi, views, m, st in reqs:
+            got = to_np(ctx.request_outputs(t))
+            if m is None:
+                solo = to_np(ctx.trace_views(frames[fi][1], views, st))
+            else:
+                solo = to_np(ctx.trace_mesh(frames[fi][1], views, m, st))
+                seen.update(np.unique(got["surface"]).tolist())
+            torch.cuda.synchronize()
+            for k in solo:
+                assert np.array_equal(got[k].view(np.uint8), solo[k].view(np.uint8)), (t, k)
+            ctx.request_release(t)
+        assert {1, 2}.issubset(seen), seen
+        ctx.server_stop()
+        for m in meshes[1:]:
+            m.release()
+    finally:
+        ctx.close()
+
+
+def test_serve_mesh_errors(haze):
+    """hz_submit_mesh refuses a mesh of another context and steps longer than
+    the mesh's reach, at submission."""
+    from tests.test_gpu_scene import _boards
+    print("case serve mesh errors", flush=True)
+    ctx, other = haze.Context(0), haze.Context(0)
+    try:
+        wl, field = _frames(ctx, haze, n=1)[0]
+        st_a, _ = W.make_steps(wl.grid)
+        tris = W.tessellate_quads(_boards(wl.grid.lo, wl.grid.hi), 2)
+        short = ctx.mesh_create(*tris, reach=0.5 * st_a.ds_max)
+        foreign = other.mesh_create(*tris, reach=st_a.ds_max)
+        ctx.server_start(slots=1, max_batch_rays=1 << 16)
+        views = _random_request(np.random.default_rng(1), wl.grid)
+        with pytest.raises(haze.HazeError) as e:
+            ctx.submit(field, views, st_a, mesh=short)
+        assert e.value.status == haze.E_INVALID
+        with pytest.raises(haze.HazeError) as e:
+            ctx.submit(field, views, st_a, mesh=foreign)
+        assert e.value.status == haze.E_INVALID
+        ctx.server_stop()
+        short.release()
+        foreign.release()
+    finally:
+        other.close()
+        ctx.close()
