@@ -146,8 +146,8 @@ hz_status hz_profile_read(hz_ctx *ctx, const char *kernel, double *total_ms, int
 
 /* Particle set, structure of arrays.  x, y, z, m are device pointers to n
  * float32 values each (positions in metres, masses in kg), caller-owned and
- * only read.  Particles farther than 2h from the grid box contribute nothing
- * and are skipped. */
+ * only read.  Particles farther than 2h from the grid box, or whose mass is
+ * not finite, contribute nothing and are skipped. */
 typedef struct {
     int64_t n;
     const float *x, *y, *z, *m;

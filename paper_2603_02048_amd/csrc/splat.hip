@@ -17,9 +17,10 @@
 //                  (stable order); (x, y, z, m) into cell-sorted float4 records
 //   k_splat        one workgroup per 8x8x4 or 8x8x8 voxel brick, its cell-list
 //                  rows dealt to four waves: every lane owns a column of
-//                  voxels and the wave's lanes walk the same candidate
-//                  particles (wave-uniform scalar loads), culled by the
-//                  brick-to-row distance, summing m_j W in a fixed order
+//                  voxels; each candidate particle is culled to the planes
+//                  it reaches (64 candidates at a time, one per lane), then
+//                  the wave's lanes walk the remaining candidates together
+//                  (wave-uniform scalar loads), summing m_j W in a fixed order
 //   k_splat_scatter  alternative: voxel tiles with 64-bit fixed-point LDS
 //                  accumulators, particles walking their footprints (more
 //                  accurate, bitwise repeatable, but about 2x slower than the
@@ -68,14 +69,14 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
         const int cx = cell_coord(x[i], cg.clo[0], cg.inv_cell, cg.nc[0]);
         const int cy = cell_coord(y[i], cg.clo[1], cg.inv_cell, cg.nc[1]);
         const int cz = cell_coord(z[i], cg.clo[2], cg.inv_cell, cg.nc[2]);
+        // a particle outside the grown box, or with a mass that is not
+        // finite, is in no cell and adds nothing
+        const float am = fabsf(m[i]);
         uint32_t id = 0xffffffffu;
-        if (cx >= 0 && cy >= 0 && cz >= 0) {
+        if (cx >= 0 && cy >= 0 && cz >= 0 && isfinite(am)) {
             id = (uint32_t)((cz * cg.nc[1] + cy) * cg.nc[0] + cx);
             lrank[i] = atomicAdd(&count[id], 1u);
-            if (MMAX) {
-                const float am = fabsf(m[i]);
-                if (am > 0.0f && isfinite(am)) mbits = __float_as_uint(am);
-            }
+            if (MMAX && am > 0.0f) mbits = __float_as_uint(am);
         }
         cid[i] = id;
     }
@@ -299,89 +300,92 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
     sorted[b + rank] = rec;
 }
 
-// Adds one candidate particle's M4-spline terms to voxels V0..V1 of the lane's
-// column (the others are known to be out of reach).
-template <int V0, int V1>
-__device__ __forceinline__ void splat_candidate(const SplatParams &P, float cx, float cy, const float *cz,
-                                                const float4 &q, float *acc)
+// M4 spline (Eq. 12) through two clamped variables.  With q = r / h,
+// t = max(1 - q/2, 0) and s = max(1 - q, 0), both in [0, 1]:
+//   4 W(q) / sigma = (2 - q)^3 - 4 (1 - q)^3 = 8 t^3 - 4 s^3   (q < 1)
+//                  = (2 - q)^3               = 8 t^3           (1 <= q < 2)
+//                  = 0                                        (q >= 2),
+// so sum_j m_j W = (sigma / 4) (8 A - 4 B) with A = sum m t^3 over the
+// support sphere (q < 2) and B = sum m s^3 over the inner sphere (q < 1).
+// A lane outside a sphere gets t = 0 (or s = 0) from the clamp and adds an
+// exact zero, so a plane needs no per-lane test: a wave-uniform cull decides
+// which planes a candidate visits.
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+// acc += m w, with m wave-uniform, updating acc in its own register (so that a
+// plane's branch needs no copies of the sums where it joins the path that
+// skipped it)
+__device__ __forceinline__ void acc_add(float &acc, float m, float w)
 {
-    const float dx = cx - q.x, dy = cy - q.y;
+    asm("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "s"(m), "v"(w));
+}
+
+// Per-lane state of the gather: the column's voxel centres and the two sums
+// per voxel.
+template <int BZ>
+struct Column {
+    float cx, cy;
+    float cz[BZ];
+    float a[BZ], b[BZ];
+};
+
+// Candidate q at plane V, dxy = the lane's squared x-y distance to q; the
+// inner term too when the inner sphere reaches the plane (wave-uniform).
+template <int V, int BZ>
+__device__ __forceinline__ void plane_terms(Column<BZ> &c, float dxy, const float4 &q, bool inner, float nhalf_inv_h,
+                                            float ninv_h)
+{
+    const float dz = c.cz[V] - q.z;
+    const float r = __builtin_amdgcn_sqrtf(fmaf(dz, dz, dxy));
+    const float t = clamp01(fmaf(r, nhalf_inv_h, 1.0f));
+    acc_add(c.a[V], q.w, t * t * t);
+    if (inner) {
+        const float s = clamp01(fmaf(r, ninv_h, 1.0f));
+        acc_add(c.b[V], q.w, s * s * s);
+    }
+}
+
+// The planes of the wave-uniform masks, in order (a uniform branch each).
+template <int V, int BZ>
+__device__ __forceinline__ void planes(uint32_t om, uint32_t im, Column<BZ> &c, float dxy, const float4 &q,
+                                       float nhalf_inv_h, float ninv_h)
+{
+    if constexpr (V < BZ) {
+        if (om & (1u << V)) plane_terms<V, BZ>(c, dxy, q, (im & (1u << V)) != 0u, nhalf_inv_h, ninv_h);
+        planes<V + 1, BZ>(om, im, c, dxy, q, nhalf_inv_h, ninv_h);
+    }
+}
+
+// One candidate: the cull's wave-uniform word holds the planes its support
+// sphere reaches (bits 0-7) and those its inner sphere reaches (bits 8-15, a
+// subset).
+template <int BZ>
+__device__ __forceinline__ void gather_candidate(Column<BZ> &c, const float4 &q, uint32_t pk, float nhalf_inv_h,
+                                                 float ninv_h)
+{
+    const float dx = c.cx - q.x, dy = c.cy - q.y;
     const float dxy = fmaf(dx, dx, dy * dy);
-    if (dxy < P.support2) {
-#pragma unroll
-        for (int v = V0; v <= V1; ++v) {
-            const float dz = cz[v] - q.z;
-            const float r2 = fmaf(dz, dz, dxy);
-            if (r2 < P.support2) {
-                // M4 spline times 4: 4 - 6q^2 + 3q^3 (q < 1), (2 - q)^3 (1 <= q < 2).
-                // With u = 1 - q (in (-1, 1] here) both pieces are
-                // 1 + 3u + 3u^2 + c u^3, c = -3 for u > 0 and 1 otherwise, and
-                // c u = min(u, -3u): a multiply and a min pick the piece (no
-                // compare-and-select, whose mask write stalls the next
-                // instruction), then Horner (the factor 1/4 is in the final scale)
-                const float u = fmaf(-__builtin_amdgcn_sqrtf(r2), P.inv_h, 1.0f);
-                const float cu = fminf(u, -3.0f * u);
-                const float w4 = fmaf(fmaf(3.0f + cu, u, 3.0f), u, 1.0f);
-                acc[v] = fmaf(q.w, w4, acc[v]);
-            }
-        }
-    }
-}
-
-// The candidates [s0, s1) of one cell row against voxels V0..V1 of the column;
-// two records per iteration: one wider scalar load and one wait for both, half
-// the loop overhead (the terms are still added in index order).
-template <int V0, int V1>
-__device__ __forceinline__ void splat_row(const SplatParams &P, float cx, float cy, const float *cz,
-                                          const float4 *__restrict__ parts, uint32_t s0, uint32_t s1, float *acc)
-{
-    uint32_t s = s0;
-    for (; s + 1 < s1; s += 2) {
-        const float4 qa = parts[s], qb = parts[s + 1];
-        splat_candidate<V0, V1>(P, cx, cy, cz, qa, acc);
-        splat_candidate<V0, V1>(P, cx, cy, cz, qb, acc);
-    }
-    if (s < s1) splat_candidate<V0, V1>(P, cx, cy, cz, parts[s], acc);
-}
-
-// splat_row over planes 0..v1 (none when v1 < 0), v1 wave-uniform.
-template <int V1>
-__device__ __forceinline__ void splat_row_upto(int v1, const SplatParams &P, float cx, float cy, const float *cz,
-                                               const float4 *__restrict__ parts, uint32_t s0, uint32_t s1,
-                                               float *acc)
-{
-    if constexpr (V1 >= 0) {
-        if (v1 == V1) splat_row<0, V1>(P, cx, cy, cz, parts, s0, s1, acc);
-        else splat_row_upto<V1 - 1>(v1, P, cx, cy, cz, parts, s0, s1, acc);
-    }
-}
-
-// splat_row over planes v0..BZ-1 (none when v0 >= BZ), 1 <= v0, v0 wave-uniform.
-template <int BZ, int V0 = 1>
-__device__ __forceinline__ void splat_row_from(int v0, const SplatParams &P, float cx, float cy, const float *cz,
-                                               const float4 *__restrict__ parts, uint32_t s0, uint32_t s1,
-                                               float *acc)
-{
-    if constexpr (V0 < BZ) {
-        if (v0 == V0) splat_row<V0, BZ - 1>(P, cx, cy, cz, parts, s0, s1, acc);
-        else splat_row_from<BZ, V0 + 1>(v0, P, cx, cy, cz, parts, s0, s1, acc);
-    }
+    planes<0, BZ>(pk & 0xffu, (pk >> 8) & 0xffu, c, dxy, q, nhalf_inv_h, ninv_h);
 }
 
 // One workgroup per brick of 8 x 8 x BZ voxels (BZ = 4 or 8); in each of its
-// four waves, lane (lane & 7, lane >> 3) owns the column of BZ voxels along z.  The brick's
-// cell-list rows near it (each row's x-range cut to the support circle) are
-// dealt round-robin to its four waves, whose lanes walk the row's candidate
-// particles through wave-uniform scalar loads; the x-y distance is computed
-// once per candidate and shared by the lane's column, and a candidate or
-// voxel that no lane reaches is skipped wave-wide.  The four partial sums are
-// added in wave order through LDS, and each wave adds its terms in row order,
-// then particle index order, so the field is bitwise repeatable.  Splitting a
-// brick four ways gives four times as many work units as wave slots, so the
-// dispatcher balances bricks of unequal cost.  Workgroups are remapped so
-// that each XCD (workgroups are dealt round-robin over the 8 XCDs) walks a
-// contiguous run of bricks and keeps its particle rows in its own L2.
-// waves per brick (262,144 particles on a 128^3 grid: 4 waves 0.565 ms; 8: 0.621 ms; 1: 0.649 ms)
+// four waves, lane (lane & 7, lane >> 3) owns the column of BZ voxels along z.
+// The brick's cell-list rows near it (each row's x-range cut to the support
+// circle) are dealt round-robin to its four waves.  A wave culls a row's
+// candidates 64 at a time, one per lane: from the candidate's x-y distance to
+// the brick's box of columns it finds the planes its support sphere reaches
+// for some column, and those its inner sphere reaches (both as exact as
+// testing every lane: a plane is culled only when no lane can be in reach).
+// The candidates left are then taken in index order, each as wave-uniform
+// scalar loads; its x-y distance is computed once per lane and shared by the
+// column, and each plane in range costs seven instructions per lane, with no
+// per-lane test or branch.  The four partial sums are added in wave order
+// through LDS, and each wave adds its terms in row order, then particle index
+// order, so the field is bitwise repeatable.  Splitting a brick four ways
+// gives four times as many work units as wave slots, so the dispatcher
+// balances bricks of unequal cost.  Workgroups are remapped so that each XCD
+// (workgroups are dealt round-robin over the 8 XCDs) walks a contiguous run of
+// bricks and keeps its particle rows in its own L2.
 constexpr int SPLAT_WAVES = 4;
 
 template <int BZ>
@@ -399,13 +403,18 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     const int32_t by = (brick / P.nbx) % P.nby;
     const int32_t bz = brick / (P.nbx * P.nby);
     const int32_t vx = bx * SPLAT_BX + (lane & 7), vy = by * SPLAT_BY + (lane >> 3), vz0 = bz * BZ;
-    const float cx = P.lo[0] + ((float)vx + 0.5f) * P.sp[0];
-    const float cy = P.lo[1] + ((float)vy + 0.5f) * P.sp[1];
-    float cz[BZ];
+    Column<BZ> col;
+    col.cx = P.lo[0] + ((float)vx + 0.5f) * P.sp[0];
+    col.cy = P.lo[1] + ((float)vy + 0.5f) * P.sp[1];
 #pragma unroll
-    for (int v = 0; v < BZ; ++v) cz[v] = P.lo[2] + ((float)(vz0 + v) + 0.5f) * P.sp[2];
+    for (int v = 0; v < BZ; ++v) {
+        col.cz[v] = P.lo[2] + ((float)(vz0 + v) + 0.5f) * P.sp[2];
+        col.a[v] = 0.0f;
+        col.b[v] = 0.0f;
+    }
 
-    // brick AABB of voxel centres (wave-uniform)
+    // brick AABB of voxel centres (wave-uniform; the x-y faces are the centres
+    // of the first and last columns, bit for bit as the lanes compute them)
     float blo[3], bhi[3];
     {
         const int32_t b0[3] = {bx * SPLAT_BX, by * SPLAT_BY, vz0};
@@ -418,6 +427,12 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     }
     const CellGrid &cg = P.cg;
     const float R = 2.0f * P.h;
+    const float nhalf_inv_h = -0.5f * P.inv_h, ninv_h = -P.inv_h;
+    // cull bounds: squared radii grown by 0.1% and plane ranges by 1% of a
+    // plane, so that rounding never drops a plane some lane reaches (a plane
+    // visited needlessly adds exact zeros)
+    const float ro2 = 1.001f * P.support2, ri2 = 1.001f * P.h * P.h;
+    const float inv_spz = 1.0f / P.sp[2];
     // conservative cell ranges (one cell of slack absorbs rounding)
     const int cz0 = max(0, (int)floorf((blo[2] - R - cg.clo[2]) * cg.inv_cell) - 1);
     const int cz1 = min(cg.nc[2] - 1, (int)floorf((bhi[2] + R - cg.clo[2]) * cg.inv_cell) + 1);
@@ -425,18 +440,18 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     const int cy1 = min(cg.nc[1] - 1, (int)floorf((bhi[1] + R - cg.clo[1]) * cg.inv_cell) + 1);
     const int ny = cy1 - cy0 + 1;
 
-    float acc[BZ];
-#pragma unroll
-    for (int v = 0; v < BZ; ++v) acc[v] = 0.0f;
     // rows (kz, ky) in order, every SPLAT_WAVES-th from the wave's index (no rows
     // if the y range is empty, so the row stepping below always advances); no
     // rows, and NaN voxels, when the cell-list scan failed
     const bool bad = *fail != 0u;
     int kz = ny >= 1 && !bad ? cz0 : cz1 + 1, ky = cy0 + wave;
     for (;;) {
-        while (ky > cy1) {
-            ky -= ny;
-            ++kz;
+        // (wrapping past the y range without a loop, which would cost copies
+        // of the sums around it)
+        if (ky > cy1 && ny >= 1) {
+            const int k = (ky - cy1 + ny - 1) / ny;
+            ky -= k * ny;
+            kz += k;
         }
         if (kz > cz1) break;
         const int kyr = ky;
@@ -446,48 +461,66 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
         const float yl = cg.clo[1] + (float)kyr * cg.cell;
         const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
         // 1.0001 R^2 keeps the cull conservative under rounding (and the
-        // 1-ulp hardware square root)
+        // 1-ulp hardware square root); a row out of reach gets an empty range
+        // (one path through the loop body keeps the sums in the same registers)
         const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
-        if (rem <= 0.0f) continue;
-        const float dxm = __builtin_amdgcn_sqrtf(rem);
+        const float dxm = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f));
         const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
         const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
-        if (kx0 > kx1) continue;
-        const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
-        const uint32_t s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
-        const uint32_t s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
-        // The row's particles lie in the z-cell [zl, zl + cell]: voxel planes
-        // farther than R from it (a margin of 0.1% of R covers the rounding of
-        // cell ids) are skipped for the whole row, through a copy of the loop
-        // specialised to the planes in reach (2.6 of 8 planes per candidate at
-        // 128^3 with 2:1 voxels, 1.4 of 8 at 256^3).  When the reach (cell + 2R)
-        // is longer than the brick, only one end is ever cut; a row with both
-        // ends cut takes the full loop, whose per-voxel test rejects the rest.
-        const float Rm = 1.001f * R;
-        const float zlo = zl - Rm, zhi = zl + cg.cell + Rm;
-        int below = 0, above = 0;
-#pragma unroll
-        for (int v = 0; v < BZ; ++v) {
-            below += cz[v] <= zlo;
-            above += cz[v] >= zhi;
+        uint32_t s0 = 0u, s1 = 0u;
+        if (rem > 0.0f && kx0 <= kx1) {
+            const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
+            s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
+            s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
         }
-        const int v0 = __builtin_amdgcn_readfirstlane(below);
-        const int v1 = __builtin_amdgcn_readfirstlane(BZ - 1 - above);
-        if (v0 > v1) continue;   // no plane in reach
-        if (v0 == 0) splat_row_upto<BZ - 1>(v1, P, cx, cy, cz, parts, s0, s1, acc);
-        else if (v1 == BZ - 1) splat_row_from<BZ>(v0, P, cx, cy, cz, parts, s0, s1, acc);
-        else splat_row<0, BZ - 1>(P, cx, cy, cz, parts, s0, s1, acc);
+        for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
+            // the cull: lane l takes candidate c0 + l
+            const uint32_t idx = c0 + (uint32_t)lane;
+            bool reach = false;
+            uint32_t pk = 0u;
+            if (idx < s1) {
+                const float4 p = parts[idx];
+                const float ex = fmaxf(fmaxf(blo[0] - p.x, p.x - bhi[0]), 0.0f);
+                const float ey = fmaxf(fmaxf(blo[1] - p.y, p.y - bhi[1]), 0.0f);
+                const float d2 = fmaf(ex, ex, ey * ey);
+                const float zr = (p.z - blo[2]) * inv_spz;   // in planes from plane 0
+                const float ho = __builtin_amdgcn_sqrtf(fmaxf(ro2 - d2, 0.0f)) * inv_spz + 0.01f;
+                const float hi = __builtin_amdgcn_sqrtf(fmaxf(ri2 - d2, 0.0f)) * inv_spz + 0.01f;
+                // planes v0..v1 as a bit mask (empty when v0 > v1)
+                const auto span = [](float z0, float z1) -> uint32_t {
+                    const int v0 = max(0, (int)ceilf(z0)), v1 = min(BZ - 1, (int)floorf(z1));
+                    return v0 > v1 ? 0u : ((2u << v1) - (1u << v0));
+                };
+                const uint32_t om = d2 < ro2 ? span(zr - ho, zr + ho) : 0u;
+                const uint32_t im = d2 < ri2 ? span(zr - hi, zr + hi) : 0u;
+                reach = om != 0u;
+                pk = om | (im << 8);
+            }
+            // the candidates left, in index order
+            for (uint64_t mask = __builtin_amdgcn_ballot_w64(reach); mask;) {
+                const int i = __builtin_ctzll(mask);
+                mask &= ~(1ull << i);
+                const float4 q = parts[c0 + (uint32_t)i];
+                // the whole record in registers here, ahead of the planes' branches
+                asm volatile("" ::"s"(q.x), "s"(q.y), "s"(q.z), "s"(q.w));
+                gather_candidate<BZ>(col, q, __builtin_amdgcn_readlane(pk, i), nhalf_inv_h, ninv_h);
+            }
+        }
     }
+    // this wave's share of sum m W / sigma = 2 A - B (the scale is k_gd sigma)
+    float part[BZ];
+#pragma unroll
+    for (int v = 0; v < BZ; ++v) part[v] = fmaf(2.0f, col.a[v], -col.b[v]);
     if (wave > 0) {
 #pragma unroll
-        for (int v = 0; v < BZ; ++v) partial[wave - 1][v][lane] = acc[v];
+        for (int v = 0; v < BZ; ++v) partial[wave - 1][v][lane] = part[v];
     }
     __syncthreads();
     if (wave == 0 && vx < P.res[0] && vy < P.res[1]) {
-        const float sc = bad ? __builtin_nanf("") : 0.25f * P.scale;
+        const float sc = bad ? __builtin_nanf("") : P.scale;
 #pragma unroll
         for (int v = 0; v < BZ; ++v) {
-            float sum = acc[v];
+            float sum = part[v];
 #pragma unroll
             for (int w = 0; w < SPLAT_WAVES - 1; ++w) sum += partial[w][v][lane];
             if (vz0 + v < P.res[2]) dn[((int64_t)vy * P.res[0] + vx) * P.res[2] + vz0 + v] = sum * sc;
