@@ -312,14 +312,6 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
 // which planes a candidate visits.
 __device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
-// acc += m w, with m wave-uniform, updating acc in its own register (so that a
-// plane's branch needs no copies of the sums where it joins the path that
-// skipped it)
-__device__ __forceinline__ void acc_add(float &acc, float m, float w)
-{
-    asm("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "s"(m), "v"(w));
-}
-
 // Per-lane state of the gather: the column's voxel centres and the two sums
 // per voxel.
 template <int BZ>
@@ -338,10 +330,10 @@ __device__ __forceinline__ void plane_terms(Column<BZ> &c, float dxy, const floa
     const float dz = c.cz[V] - q.z;
     const float r = __builtin_amdgcn_sqrtf(fmaf(dz, dz, dxy));
     const float t = clamp01(fmaf(r, nhalf_inv_h, 1.0f));
-    acc_add(c.a[V], q.w, t * t * t);
+    c.a[V] = fmaf(q.w, t * t * t, c.a[V]);
     if (inner) {
         const float s = clamp01(fmaf(r, ninv_h, 1.0f));
-        acc_add(c.b[V], q.w, s * s * s);
+        c.b[V] = fmaf(q.w, s * s * s, c.b[V]);
     }
 }
 
@@ -442,18 +434,23 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
 
     // rows (kz, ky) in order, every SPLAT_WAVES-th from the wave's index (no rows
     // if the y range is empty, so the row stepping below always advances); no
-    // rows, and NaN voxels, when the cell-list scan failed
+    // rows, and NaN voxels, when the cell-list scan failed.  Each pass of the
+    // loop culls the next 64 candidates of the current row and sums those
+    // left, then moves to the next row when the row is done (a row out of
+    // reach is culled as empty): one exit, at the bottom, so the sums keep
+    // their registers through the loop.
     const bool bad = *fail != 0u;
     int kz = ny >= 1 && !bad ? cz0 : cz1 + 1, ky = cy0 + wave;
-    for (;;) {
-        // (wrapping past the y range without a loop, which would cost copies
-        // of the sums around it)
+    uint32_t c0 = 0u, s1 = 0u;   // the next candidate to cull; the row's end
+    // moves to the next row; false when there is none
+    const auto next_row = [&]() -> bool {
+        // (wrapping past the y range without a loop)
         if (ky > cy1 && ny >= 1) {
             const int k = (ky - cy1 + ny - 1) / ny;
             ky -= k * ny;
             kz += k;
         }
-        if (kz > cz1) break;
+        if (kz > cz1) return false;
         const int kyr = ky;
         ky += SPLAT_WAVES;
         const float zl = cg.clo[2] + (float)kz * cg.cell;
@@ -461,51 +458,53 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
         const float yl = cg.clo[1] + (float)kyr * cg.cell;
         const float gy = fmaxf(0.0f, fmaxf(yl - bhi[1], blo[1] - (yl + cg.cell)));
         // 1.0001 R^2 keeps the cull conservative under rounding (and the
-        // 1-ulp hardware square root); a row out of reach gets an empty range
-        // (one path through the loop body keeps the sums in the same registers)
+        // 1-ulp hardware square root)
         const float rem = 1.0001f * P.support2 - gz * gz - gy * gy;
         const float dxm = __builtin_amdgcn_sqrtf(fmaxf(rem, 0.0f));
         const int kx0 = max(0, (int)floorf((blo[0] - dxm - cg.clo[0]) * cg.inv_cell));
         const int kx1 = min(cg.nc[0] - 1, (int)floorf((bhi[0] + dxm - cg.clo[0]) * cg.inv_cell));
-        uint32_t s0 = 0u, s1 = 0u;
+        c0 = s1 = 0u;
         if (rem > 0.0f && kx0 <= kx1) {
             const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
-            s0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
+            c0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
             s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
         }
-        for (uint32_t c0 = s0; c0 < s1; c0 += 64) {
-            // the cull: lane l takes candidate c0 + l
-            const uint32_t idx = c0 + (uint32_t)lane;
-            bool reach = false;
-            uint32_t pk = 0u;
-            if (idx < s1) {
-                const float4 p = parts[idx];
-                const float ex = fmaxf(fmaxf(blo[0] - p.x, p.x - bhi[0]), 0.0f);
-                const float ey = fmaxf(fmaxf(blo[1] - p.y, p.y - bhi[1]), 0.0f);
-                const float d2 = fmaf(ex, ex, ey * ey);
-                const float zr = (p.z - blo[2]) * inv_spz;   // in planes from plane 0
-                const float ho = __builtin_amdgcn_sqrtf(fmaxf(ro2 - d2, 0.0f)) * inv_spz + 0.01f;
-                const float hi = __builtin_amdgcn_sqrtf(fmaxf(ri2 - d2, 0.0f)) * inv_spz + 0.01f;
-                // planes v0..v1 as a bit mask (empty when v0 > v1)
-                const auto span = [](float z0, float z1) -> uint32_t {
-                    const int v0 = max(0, (int)ceilf(z0)), v1 = min(BZ - 1, (int)floorf(z1));
-                    return v0 > v1 ? 0u : ((2u << v1) - (1u << v0));
-                };
-                const uint32_t om = d2 < ro2 ? span(zr - ho, zr + ho) : 0u;
-                const uint32_t im = d2 < ri2 ? span(zr - hi, zr + hi) : 0u;
-                reach = om != 0u;
-                pk = om | (im << 8);
-            }
-            // the candidates left, in index order
-            for (uint64_t mask = __builtin_amdgcn_ballot_w64(reach); mask;) {
-                const int i = __builtin_ctzll(mask);
-                mask &= ~(1ull << i);
-                const float4 q = parts[c0 + (uint32_t)i];
-                // the whole record in registers here, ahead of the planes' branches
-                asm volatile("" ::"s"(q.x), "s"(q.y), "s"(q.z), "s"(q.w));
-                gather_candidate<BZ>(col, q, __builtin_amdgcn_readlane(pk, i), nhalf_inv_h, ninv_h);
-            }
+        return true;
+    };
+    for (bool more = next_row(); more;) {
+        // the cull: lane l takes candidate c0 + l
+        const uint32_t idx = c0 + (uint32_t)lane;
+        bool reach = false;
+        uint32_t pk = 0u;
+        if (idx < s1) {
+            const float4 p = parts[idx];
+            const float ex = fmaxf(fmaxf(blo[0] - p.x, p.x - bhi[0]), 0.0f);
+            const float ey = fmaxf(fmaxf(blo[1] - p.y, p.y - bhi[1]), 0.0f);
+            const float d2 = fmaf(ex, ex, ey * ey);
+            const float zr = (p.z - blo[2]) * inv_spz;   // in planes from plane 0
+            const float ho = __builtin_amdgcn_sqrtf(fmaxf(ro2 - d2, 0.0f)) * inv_spz + 0.01f;
+            const float hi = __builtin_amdgcn_sqrtf(fmaxf(ri2 - d2, 0.0f)) * inv_spz + 0.01f;
+            // planes v0..v1 as a bit mask (empty when v0 > v1)
+            const auto span = [](float z0, float z1) -> uint32_t {
+                const int v0 = max(0, (int)ceilf(z0)), v1 = min(BZ - 1, (int)floorf(z1));
+                return v0 > v1 ? 0u : ((2u << v1) - (1u << v0));
+            };
+            const uint32_t om = d2 < ro2 ? span(zr - ho, zr + ho) : 0u;
+            const uint32_t im = d2 < ri2 ? span(zr - hi, zr + hi) : 0u;
+            reach = om != 0u;
+            pk = om | (im << 8);
         }
+        // the candidates left, in index order
+        for (uint64_t mask = __builtin_amdgcn_ballot_w64(reach); mask;) {
+            const int i = __builtin_ctzll(mask);
+            mask &= ~(1ull << i);
+            const float4 q = parts[c0 + (uint32_t)i];
+            // the whole record in registers here, ahead of the planes' branches
+            asm volatile("" ::"s"(q.x), "s"(q.y), "s"(q.z), "s"(q.w));
+            gather_candidate<BZ>(col, q, __builtin_amdgcn_readlane(pk, i), nhalf_inv_h, ninv_h);
+        }
+        c0 += 64u;
+        if (c0 >= s1) more = next_row();
     }
     // this wave's share of sum m W / sigma = 2 A - B (the scale is k_gd sigma)
     float part[BZ];
