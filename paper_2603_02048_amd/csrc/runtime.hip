@@ -829,8 +829,9 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     sp.nbx = (g->res[0] + SPLAT_BX - 1) / SPLAT_BX;
     sp.nby = (g->res[1] + SPLAT_BY - 1) / SPLAT_BY;
     // brick depth: the one of 4 or 8 voxels that brings the brick closer to
-    // twice as deep as wide, the shape measured fastest with the per-row plane
-    // skip (8 unless the z spacing exceeds 2 sqrt(2) times the x-y spacing)
+    // twice as deep as wide (8 unless the z spacing exceeds 2 sqrt(2) times
+    // the x-y spacing); the deeper brick shares each candidate's cull and x-y
+    // distance among more planes
     if (c->splat_brick_z == 4 || c->splat_brick_z == 8)
         sp.bz = c->splat_brick_z;
     else
