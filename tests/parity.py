@@ -63,7 +63,7 @@ def assert_field_match(gpu_dn, gpu_g, ref_dn, ref_g, spacing, label: str = "", r
 
 
 def oracle_sensitivity(oracle, grid, dn, views, step, ray_ids=None, trials: int = 4, rel: float = 5e-7,
-                       step_rel: float = 5e-7, pos_ulps: float = 1.0, seed: int = 0) -> dict:
+                       step_rel: float = 5e-7, pos_ulps: float = 1.0, seed: int = 0, tracer=None) -> dict:
     """Per-ray spread of the FP64 oracle's own answer under perturbations of
     the size of the FP32 path's rounding, the largest over all trials:
       * the delta-n grid times (1 + rel N(0,1)) per voxel, `trials` draws (the
@@ -76,11 +76,15 @@ def oracle_sensitivity(oracle, grid, dn, views, step, ray_ids=None, trials: int 
         length carries a few ulps of rounding.
     Rays in strongly focusing regions (caustics, grazing exits through the
     steep band at the box faces) move by more than the fixed tolerances under
-    such perturbations: no FP32 implementation can be held closer than that."""
+    such perturbations: no FP32 implementation can be held closer than that.
+    `tracer(medium, views, step, ray_ids)` replaces oracle.trace_views (for
+    scenes: the same perturbations, the scene traced as well)."""
     import dataclasses
     from paper_2603_02048_amd import workloads as W
+    if tracer is None:
+        tracer = lambda md, v, st, ray_ids: oracle.trace_views(md, v, st, ray_ids=ray_ids)
     base_md = oracle.Medium.from_grid(grid, dn)
-    base = oracle.trace_views(base_md, views, step, ray_ids=ray_ids)
+    base = tracer(base_md, views, step, ray_ids)
     rng = np.random.default_rng(seed)
     s = dict(pos=0.0, dir=0.0, px=0.0)
     runs = [(oracle.Medium.from_grid(grid, dn * (1.0 + rel * rng.standard_normal(dn.shape))), step)
@@ -95,7 +99,7 @@ def oracle_sensitivity(oracle, grid, dn, views, step, ray_ids=None, trials: int 
         runs += [(base_md, dataclasses.replace(step, theta_max=step.theta_max * (1.0 + f * step_rel)))
                  for f in (-1.0, 1.0)]
     for md, st in runs:
-        r = oracle.trace_views(md, views, st, ray_ids=ray_ids)
+        r = tracer(md, views, st, ray_ids)
         s["pos"] = np.maximum(s["pos"], np.linalg.norm(r["exit_pos"] - base["exit_pos"], axis=1) / grid.voxel)
         s["dir"] = np.maximum(s["dir"], np.linalg.norm(r["exit_dir"] - base["exit_dir"], axis=1))
         dd = np.abs(r["disp"] - base["disp"]).max(axis=1)

@@ -7,7 +7,10 @@ where the shell's distance bound exceeds the step.  Which surface a ray meets
 is decided in floating point near a surface's rim: there the oracle is also
 run with the geometry shrunk and grown by a small margin, and a ray whose
 answer differs between those runs is checked only for validity.  Every other
-ray must match surface, status and the plain tolerances.  The shell must not
+ray must match surface and status, and the tolerances as on the other stress
+fields: the plain ones, or 3x the oracle's own spread under perturbations of
+the FP32 path's rounding size where that is larger, with at least 99.5% of
+the rays within the plain ones.  The shell must not
 change any result: a brute-force mesh (no shell) gives the same bits, with
 many more exact tests per ray.
 """
@@ -17,7 +20,7 @@ import torch
 
 import oracle
 from paper_2603_02048_amd import workloads as W
-from tests.parity import assert_rays_match, to_np
+from tests.parity import assert_rays_match_conditioned, oracle_sensitivity, to_np
 from tests.test_gpu_scene import _boards, _inflate, _views
 
 pytestmark = pytest.mark.gpu
@@ -40,9 +43,14 @@ def ctx(haze):
 
 
 def _compare(g, md, views, geo, st, voxel, label):
-    """geo: (tris, surf) and the shrunk and grown variants [(tris, surf)] * 3."""
+    """geo: (tris, surf) and the shrunk and grown variants [(tris, surf)] * 3.
+    The fields here are stress fields (K_GD x 200), so rays are held to the
+    plain tolerances or, where the oracle's own answer moves more under
+    perturbations of the FP32 path's rounding size, to 3x that spread."""
     (tr, sf), (tlo, slo), (thi, shi) = geo
     ref = oracle.trace_mesh(md, views, tr, sf, st)
+    sens = oracle_sensitivity(oracle, md.grid, md.arrays[0], views, st,
+                              tracer=lambda m, v, s, ray_ids: oracle.trace_mesh(m, v, tr, sf, s, ray_ids=ray_ids))
     lo_ = oracle.trace_mesh(md, views, tlo, slo, st)
     hi_ = oracle.trace_mesh(md, views, thi, shi, st)
     amb = (lo_["surface"] != hi_["surface"]) | (lo_["surface"] != ref["surface"])
@@ -53,8 +61,9 @@ def _compare(g, md, views, geo, st, voxel, label):
     assert ok_amb[amb].all(), label
     keep = ~amb
     assert np.array_equal(g["surface"][keep], ref["surface"][keep]), label
-    assert_rays_match({k: v[keep] for k, v in g.items() if k not in ("surface", "tri_tests")},
-                      {k: v[keep] for k, v in ref.items() if k != "surface"}, voxel, label)
+    assert_rays_match_conditioned({k: v[keep] for k, v in g.items() if k not in ("surface", "tri_tests")},
+                                  {k: v[keep] for k, v in ref.items() if k != "surface"},
+                                  {k: v[keep] for k, v in sens.items()}, voxel, label)
     return ref
 
 

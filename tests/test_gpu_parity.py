@@ -106,6 +106,41 @@ def test_splat_is_bitwise_repeatable(ctx, haze, method):
         _default(ctx)
 
 
+@pytest.mark.parametrize("method", ["gather", "gather8", "scatter"])
+def test_splat_skips_nonfinite_masses(ctx, haze, method):
+    """Particles whose mass is NaN or infinite add nothing: the field with a
+    few of them interleaved is bitwise the field without them (the others keep
+    their relative order, so every voxel's sum runs in the same order)."""
+    _use(ctx, method)
+    try:
+        wl = W.make_small(seed=5, n=4000)
+        p = wl.particles
+        rng = np.random.default_rng(5)
+        k = 7
+        at = np.sort(rng.choice(p.n + k, size=k, replace=False))
+        keep = np.setdiff1d(np.arange(p.n + k), at)
+        lo, hi = np.asarray(wl.grid.lo), np.asarray(wl.grid.hi)
+        def merged(a, extra):
+            out = np.empty(p.n + k, np.float32)
+            out[keep] = a
+            out[at] = extra
+            return out
+        pos = lo + (hi - lo) * rng.random((k, 3))
+        bad_m = np.array([np.nan, np.inf, -np.inf, np.nan, np.inf, -np.nan, np.inf], np.float32)
+        both = W.Particles(merged(p.x, pos[:, 0]), merged(p.y, pos[:, 1]), merged(p.z, pos[:, 2]), merged(p.m, bad_m))
+        print(f"case non-finite masses {method}: {k} of {p.n + k} particles", flush=True)
+        f1 = ctx.splat_index_field(haze.upload_particles(p), wl.grid, wl.k_gd, wl.h)
+        f2 = ctx.splat_index_field(haze.upload_particles(both), wl.grid, wl.k_gd, wl.h)
+        a, b = _field_np(ctx, f1), _field_np(ctx, f2)
+        assert np.isfinite(b[0]).all()
+        for x, y in zip(a, b):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+        f1.release()
+        f2.release()
+    finally:
+        _default(ctx)
+
+
 def test_splat_methods_on_config2(ctx, haze):
     # both splat kernels at the benchmark's size, against the oracle
     wl = W.make_config(2)
