@@ -32,9 +32,14 @@
  *     linear [z][y][x] (x fastest).
  *   - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
  *     stream) and the call returns without waiting for it.  Device faults show
- *     up as HZ_E_DEVICE on a later call.
+ *     up as HZ_E_DEVICE on a later call.  A call that reads a field built on
+ *     another stream makes its own stream wait for the field; the traces
+ *     generate their rays (which read no field data) before that wait, so ray
+ *     generation can run while the field is still being built.
  *   - Every call returns an hz_status; nothing throws or aborts across the
- *     ABI.  On an error return no output has been written and no work queued.
+ *     ABI.  On an error return no output has been written and no work queued,
+ *     except for HZ_E_DEVICE from a failed launch or stream wait, which can
+ *     come after part of the call's work was queued.
  *     hz_last_error() describes the most recent failure on the calling thread.
  *   - A context is not thread-safe, except hz_submit and hz_poll, which may be
  *     called from any thread.

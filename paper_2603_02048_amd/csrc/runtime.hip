@@ -1319,7 +1319,6 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     if (st == HZ_OK) st = scratch_acquire(c, c->hits, 4u * (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->bins, (size_t)L.nslots, s);
     if (st == HZ_OK) st = scratch_acquire(c, c->counters, kCounterBytes, s);
-    if (st == HZ_OK) st = field_order_read(c, f, s);
     if (st != HZ_OK) return st;
     PinnedSlot *staging = nullptr;
     st = staged_copy(c, c->jobs.ptr, table.data(), table.size(), s, &staging);
@@ -1339,6 +1338,19 @@ static hz_status trace_impl(hz_ctx *c, const hz_field *fc, const hz_view *views,
     const KTimer t0 = prof_timer(c, "raygen");
     HZ_HIP(launch_raygen(L, clear, s, t0), "raygen launch");
     prof_commit(c, "raygen", t0);
+    // ray generation reads no field data, so only the march waits for the
+    // field's construction: on another stream than the splat's, ray
+    // generation runs beside it
+    st = field_order_read(c, f, s);
+    if (st != HZ_OK) {
+        // the ray generation just launched still uses the scratch
+        CallMark m;
+        if (mark_issue(c, s, &m) == HZ_OK) {
+            for (Scratch *b : {&c->jobs, &c->hits, &c->bins, &c->counters}) b->last = m;
+            staging->last = m;
+        }
+        return st;
+    }
     const KTimer t1 = prof_timer(c, "march");
     HZ_HIP(launch_march(dt, L, blocks, s, t1), "march launch");
     prof_commit(c, "march", t1);
