@@ -321,14 +321,14 @@ struct Column {
     float a[BZ], b[BZ];
 };
 
-// Candidate q at plane V, dxy = the lane's squared x-y distance to q; the
-// inner term too when the inner sphere reaches the plane (wave-uniform).
+// Candidate q at plane V, dxy = the lane's squared x-y distance to q and
+// dz[V] = z_V - z_q (wave-uniform); the inner term too when the inner sphere
+// reaches the plane (wave-uniform).
 template <int V, int BZ>
-__device__ __forceinline__ void plane_terms(Column<BZ> &c, float dxy, const float4 &q, bool inner, float nhalf_inv_h,
-                                            float ninv_h)
+__device__ __forceinline__ void plane_terms(Column<BZ> &c, float dxy, const float *dz, const float4 &q, bool inner,
+                                            float nhalf_inv_h, float ninv_h)
 {
-    const float dz = c.cz[V] - q.z;
-    const float r = __builtin_amdgcn_sqrtf(fmaf(dz, dz, dxy));
+    const float r = __builtin_amdgcn_sqrtf(fmaf(dz[V], dz[V], dxy));
     const float t = clamp01(fmaf(r, nhalf_inv_h, 1.0f));
     c.a[V] = fmaf(q.w, t * t * t, c.a[V]);
     if (inner) {
@@ -339,12 +339,12 @@ __device__ __forceinline__ void plane_terms(Column<BZ> &c, float dxy, const floa
 
 // The planes of the wave-uniform masks, in order (a uniform branch each).
 template <int V, int BZ>
-__device__ __forceinline__ void planes(uint32_t om, uint32_t im, Column<BZ> &c, float dxy, const float4 &q,
-                                       float nhalf_inv_h, float ninv_h)
+__device__ __forceinline__ void planes(uint32_t om, uint32_t im, Column<BZ> &c, float dxy, const float *dz,
+                                       const float4 &q, float nhalf_inv_h, float ninv_h)
 {
     if constexpr (V < BZ) {
-        if (om & (1u << V)) plane_terms<V, BZ>(c, dxy, q, (im & (1u << V)) != 0u, nhalf_inv_h, ninv_h);
-        planes<V + 1, BZ>(om, im, c, dxy, q, nhalf_inv_h, ninv_h);
+        if (om & (1u << V)) plane_terms<V, BZ>(c, dxy, dz, q, (im & (1u << V)) != 0u, nhalf_inv_h, ninv_h);
+        planes<V + 1, BZ>(om, im, c, dxy, dz, q, nhalf_inv_h, ninv_h);
     }
 }
 
@@ -352,12 +352,12 @@ __device__ __forceinline__ void planes(uint32_t om, uint32_t im, Column<BZ> &c, 
 // sphere reaches (bits 0-7) and those its inner sphere reaches (bits 8-15, a
 // subset).
 template <int BZ>
-__device__ __forceinline__ void gather_candidate(Column<BZ> &c, const float4 &q, uint32_t pk, float nhalf_inv_h,
-                                                 float ninv_h)
+__device__ __forceinline__ void gather_candidate(Column<BZ> &c, const float4 &q, const float *dz, uint32_t pk,
+                                                 float nhalf_inv_h, float ninv_h)
 {
     const float dx = c.cx - q.x, dy = c.cy - q.y;
     const float dxy = fmaf(dx, dx, dy * dy);
-    planes<0, BZ>(pk & 0xffu, (pk >> 8) & 0xffu, c, dxy, q, nhalf_inv_h, ninv_h);
+    planes<0, BZ>(pk & 0xffu, (pk >> 8) & 0xffu, c, dxy, dz, q, nhalf_inv_h, ninv_h);
 }
 
 // One workgroup per brick of 8 x 8 x BZ voxels (BZ = 4 or 8); in each of its
@@ -370,8 +370,10 @@ __device__ __forceinline__ void gather_candidate(Column<BZ> &c, const float4 &q,
 // testing every lane: a plane is culled only when no lane can be in reach).
 // The candidates left are then taken in index order, each as wave-uniform
 // scalar loads; its x-y distance is computed once per lane and shared by the
-// column, and each plane in range costs seven instructions per lane, with no
-// per-lane test or branch.  The four partial sums are added in wave order
+// column; the planes' z offsets, the same for every lane, come from the
+// candidate's cull lane through LDS, and each plane in range costs six
+// instructions per lane, with no per-lane test or branch.  The four partial
+// sums are added in wave order
 // through LDS, and each wave adds its terms in row order, then particle index
 // order, so the field is bitwise repeatable.  Splitting a brick four ways
 // gives four times as many work units as wave slots, so the dispatcher
@@ -387,6 +389,10 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
                                                             const uint32_t *__restrict__ fail)
 {
     __shared__ float partial[SPLAT_WAVES - 1][BZ][64];
+    // per wave and culled candidate: z_v - z_j for the brick's planes (the
+    // same for every lane), read back as a broadcast instead of one
+    // subtraction per lane and plane
+    __shared__ float4 dzs[SPLAT_WAVES][64][BZ / 4];
     const int32_t brick = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
     if (brick >= nbricks) return;   // uniform over the workgroup
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -493,15 +499,31 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
             const uint32_t im = d2 < ri2 ? span(zr - hi, zr + hi) : 0u;
             reach = om != 0u;
             pk = om | (im << 8);
+#pragma unroll
+            for (int v4 = 0; v4 < BZ / 4; ++v4)
+                dzs[wave][lane][v4] = make_float4(col.cz[4 * v4] - p.z, col.cz[4 * v4 + 1] - p.z,
+                                                  col.cz[4 * v4 + 2] - p.z, col.cz[4 * v4 + 3] - p.z);
         }
         // the candidates left, in index order
         for (uint64_t mask = __builtin_amdgcn_ballot_w64(reach); mask;) {
             const int i = __builtin_ctzll(mask);
             mask &= ~(1ull << i);
+            float dz[BZ];
+#pragma unroll
+            for (int v4 = 0; v4 < BZ / 4; ++v4) {
+                const float4 d = dzs[wave][i][v4];
+                dz[4 * v4] = d.x;
+                dz[4 * v4 + 1] = d.y;
+                dz[4 * v4 + 2] = d.z;
+                dz[4 * v4 + 3] = d.w;
+            }
             const float4 q = parts[c0 + (uint32_t)i];
-            // the whole record in registers here, ahead of the planes' branches
+            // the record and the offsets in registers here, ahead of the
+            // planes' branches
             asm volatile("" ::"s"(q.x), "s"(q.y), "s"(q.z), "s"(q.w));
-            gather_candidate<BZ>(col, q, __builtin_amdgcn_readlane(pk, i), nhalf_inv_h, ninv_h);
+#pragma unroll
+            for (int v = 0; v < BZ; v += 4) asm volatile("" ::"v"(dz[v]), "v"(dz[v + 1]), "v"(dz[v + 2]), "v"(dz[v + 3]));
+            gather_candidate<BZ>(col, q, dz, __builtin_amdgcn_readlane(pk, i), nhalf_inv_h, ninv_h);
         }
         c0 += 64u;
         if (c0 >= s1) more = next_row();
