@@ -377,15 +377,16 @@ __device__ __forceinline__ void gather_candidate(Column<BZ> &c, const float4 &q,
 // through LDS, and each wave adds its terms in row order, then particle index
 // order, so the field is bitwise repeatable.  Splitting a brick four ways
 // gives four times as many work units as wave slots, so the dispatcher
-// balances bricks of unequal cost.  Workgroups are remapped so that each XCD
-// (workgroups are dealt round-robin over the 8 XCDs) walks a contiguous run of
-// bricks and keeps its particle rows in its own L2.
+// balances bricks of unequal cost.  Workgroup i takes brick i: the hardware
+// deals workgroups round-robin over the 8 XCDs, so each XCD's share is spread
+// over the whole grid (faster than giving each XCD a contiguous run of bricks
+// for its own L2: this kernel is bound by instruction issue, not by traffic).
 constexpr int SPLAT_WAVES = 4;
 
 template <int BZ>
 __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
                                                             const float4 *__restrict__ parts, int32_t nbricks,
-                                                            int32_t per_xcd, float *__restrict__ dn,
+                                                            float *__restrict__ dn,
                                                             const uint32_t *__restrict__ fail)
 {
     __shared__ float partial[SPLAT_WAVES - 1][BZ][64];
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     // same for every lane), read back as a broadcast instead of one
     // subtraction per lane and plane
     __shared__ float4 dzs[SPLAT_WAVES][64][BZ / 4];
-    const int32_t brick = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    const int32_t brick = (int32_t)blockIdx.x;
     if (brick >= nbricks) return;   // uniform over the workgroup
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -919,13 +920,12 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
                         const uint32_t *fail, hipStream_t s, const KTimer &t)
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
-    const int32_t per_xcd = (nbricks + 7) / 8;
-    const dim3 g((unsigned)(per_xcd * 8)), b(64 * SPLAT_WAVES);
+    const dim3 g((unsigned)nbricks), b(64 * SPLAT_WAVES);
     if (P.bz == 8)
-        hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn,
+        hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, dn,
                               fail);
     else
-        hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, per_xcd, dn,
+        hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, dn,
                               fail);
     return hipGetLastError();
 }
