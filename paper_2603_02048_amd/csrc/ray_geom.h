@@ -50,6 +50,41 @@ struct Ray {
     int64_t out;      // output index (flat index in subset mode, q * W + p otherwise)
 };
 
+// The view (job) whose tiles hold queue slot `slot` (not in subset mode).
+// With a wave-uniform slot (the first of a wave's 64, one 8x8 tile of one
+// view) the search runs on wave-uniform loads.
+__device__ __forceinline__ int job_of_slot(const TraceJob *jobs, int njobs, int64_t slot)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].slot_begin <= slot)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// A queue slot of view J = jobs[job] (not in subset mode) to its pixel and
+// output index; false for the padding slots of partial 8x8 tiles.
+__device__ __forceinline__ bool decode_tile_slot(const TraceJob &J, int job, int64_t slot, Ray &r)
+{
+    const int32_t local = (int32_t)(slot - J.slot_begin);
+    const int32_t tile = local >> 6;
+    const int32_t within = local & 63;
+    const int32_t ty = tile / J.tiles_x;
+    r.job = job;
+    // column-major inside the tile: consecutive slots (lanes) are vertically
+    // adjacent pixels, whose rays sit at nearly the same height; with z the
+    // field's fastest axis their gathers fall in the same cache lines, which
+    // the texture-address unit serves together
+    r.p = (tile - ty * J.tiles_x) * 8 + (within >> 3);
+    r.q = ty * 8 + (within & 7);
+    r.out = r.q * J.width + r.p;
+    return r.p < J.width && r.q < J.height;
+}
+
 // Map a queue slot to its view (job), pixel and output index; false for the
 // padding slots of partial 8x8 tiles.
 __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, Ray &r)
@@ -76,28 +111,8 @@ __device__ __forceinline__ bool decode_slot(const TraceLaunch &L, int64_t slot, 
         r.out = slot;
         return true;
     }
-    int lo = 0, hi = L.njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.jobs[mid].slot_begin <= slot)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const TraceJob &J = L.jobs[lo];
-    const int32_t local = (int32_t)(slot - J.slot_begin);
-    const int32_t tile = local >> 6;
-    const int32_t within = local & 63;
-    const int32_t ty = tile / J.tiles_x;
-    r.job = lo;
-    // column-major inside the tile: consecutive slots (lanes) are vertically
-    // adjacent pixels, whose rays sit at nearly the same height; with z the
-    // field's fastest axis their gathers fall in the same cache lines, which
-    // the texture-address unit serves together
-    r.p = (tile - ty * J.tiles_x) * 8 + (within >> 3);
-    r.q = ty * 8 + (within & 7);
-    r.out = r.q * J.width + r.p;
-    return r.p < J.width && r.q < J.height;
+    const int job = job_of_slot(L.jobs, L.njobs, slot);
+    return decode_tile_slot(L.jobs[job], job, slot, r);
 }
 
 }  // namespace haze

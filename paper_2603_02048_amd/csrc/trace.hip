@@ -241,12 +241,11 @@ __device__ __forceinline__ uint32_t *tri_tests_of(const TraceLaunch &L, const Ra
 // is a triangle, reported by its surface id, and ntests counts the exact
 // triangle tests the ray took so far).
 template <int SCENE>
-__device__ __forceinline__ void finish_ray(const TraceLaunch &L, const Ray &r, const float x[3], const float w[3],
-                                           uint32_t steps, int status, const float *hp = nullptr, int surf = -1,
-                                           uint32_t ntests = 0u)
+__device__ __forceinline__ void finish_ray(const TraceLaunch &L, const TraceJob &J, const Ray &r, const float x[3],
+                                           const float w[3], uint32_t steps, int status, const float *hp = nullptr,
+                                           int surf = -1, uint32_t ntests = 0u)
 {
     constexpr bool BOARDS = SCENE == 1 || SCENE == 2;
-    const TraceJob &J = L.jobs[r.job];
     float disp0 = __builtin_nanf(""), disp1 = __builtin_nanf("");
     int sid = 255;
     if (status != 3) {
@@ -386,7 +385,7 @@ __device__ __forceinline__ uint32_t bin_rank(int bin, uint32_t (*wcnt)[kRayBins]
 // SCENE: 0 no scene, 1 boards, 3 triangle mesh (the launch's scene kind, so
 // that the common case carries no scene code).
 template <int SCENE>
-__global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
+__global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L, const TraceJob *__restrict__ jobs)
 {
     // A tile's slots run down its columns (decode_slot), but the rays that
     // miss write their outputs here, by pixel: the 64 threads of a tile take
@@ -398,45 +397,61 @@ __global__ __launch_bounds__(kRaygenBlock) void k_raygen(TraceLaunch L)
                          (L.subset ? l : (((l & 7) << 3) | (l >> 3)));
     bool enters = false;
     int bin = 255;
-    if (slot < L.nslots) {
-        Ray r;
-        if (decode_slot(L, slot, r)) {
-            const TraceJob &J = L.jobs[r.job];
-            const float3 d3 = pixel_dir(J, r.p, r.q);
-            const float d[3] = {d3.x, d3.y, d3.z};
-            float t0, t1 = 0.0f;
-            enters = enter_volume(L.grid, J.eye, d, t0, &t1);
-            if (enters) bin = kRayBins - 1 - min(kRayBins - 1, max(0, (int)((t1 - t0) * L.inv_len_bin)));
-            if (SCENE == 3) {
-                if (enters) {
-                    // the mesh in front of the volume ends the ray before it enters;
-                    // otherwise the march continues the test count from here
-                    float tq;
-                    uint32_t nt = 0u;
-                    const int q = cast_mesh(L.mesh, J.eye, d, t0, tq, nt);
-                    if (q >= 0) {
-                        const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
-                        finish_ray<3>(L, r, J.eye, d, 0u, 0, hp, q, nt);
-                        enters = false;
-                    } else if (uint32_t *tt = tri_tests_of(L, r)) {
-                        tt[r.out] = nt;
-                    }
-                } else {
-                    finish_ray<3>(L, r, J.eye, d, 0u, 0);
-                }
-            } else if (SCENE == 1 && enters) {
-                // a board in front of the volume ends the ray before it enters
+    // one ray: pinhole direction, entry into the volume, the rays that miss
+    // (or meet the scene first) finished here
+    const auto generate = [&](const TraceJob &J, Ray &r) {
+        const float3 d3 = pixel_dir(J, r.p, r.q);
+        const float d[3] = {d3.x, d3.y, d3.z};
+        float t0, t1 = 0.0f;
+        enters = enter_volume(L.grid, J.eye, d, t0, &t1);
+        if (enters) bin = kRayBins - 1 - min(kRayBins - 1, max(0, (int)((t1 - t0) * L.inv_len_bin)));
+        if (SCENE == 3) {
+            if (enters) {
+                // the mesh in front of the volume ends the ray before it enters;
+                // otherwise the march continues the test count from here
                 float tq;
-                const int q = cast_quads(L, J.eye, d, t0, tq);
+                uint32_t nt = 0u;
+                const int q = cast_mesh(L.mesh, J.eye, d, t0, tq, nt);
                 if (q >= 0) {
                     const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
-                    finish_ray<1>(L, r, J.eye, d, 0u, 0, hp, q);
+                    finish_ray<3>(L, J, r, J.eye, d, 0u, 0, hp, q, nt);
                     enters = false;
+                } else if (uint32_t *tt = tri_tests_of(L, r)) {
+                    tt[r.out] = nt;
                 }
-            } else if (!enters) {
-                finish_ray<SCENE == 1 ? 1 : 0>(L, r, J.eye, d, 0u, 0);
+            } else {
+                finish_ray<3>(L, J, r, J.eye, d, 0u, 0);
             }
-        } else if (L.subset) {
+        } else if (SCENE == 1 && enters) {
+            // a board in front of the volume ends the ray before it enters
+            float tq;
+            const int q = cast_quads(L, J.eye, d, t0, tq);
+            if (q >= 0) {
+                const float hp[3] = {J.eye[0] + tq * d[0], J.eye[1] + tq * d[1], J.eye[2] + tq * d[2]};
+                finish_ray<1>(L, J, r, J.eye, d, 0u, 0, hp, q);
+                enters = false;
+            }
+        } else if (!enters) {
+            finish_ray<SCENE == 1 ? 1 : 0>(L, J, r, J.eye, d, 0u, 0);
+        }
+    };
+    if (!L.subset) {
+        // a wave's 64 slots are one 8x8 tile of one view: the view is found,
+        // and read, with scalar loads (`jobs` is L.jobs, which nothing here
+        // writes)
+        const uint32_t base =
+            __builtin_amdgcn_readfirstlane((uint32_t)(blockIdx.x * blockDim.x + (threadIdx.x & ~63u)));
+        if ((int64_t)base < L.nslots) {
+            const int job = job_of_slot(jobs, L.njobs, base);
+            const TraceJob &J = jobs[job];
+            Ray r;
+            if (slot < L.nslots && decode_tile_slot(J, job, slot, r)) generate(J, r);
+        }
+    } else if (slot < L.nslots) {
+        Ray r;
+        if (decode_slot(L, slot, r)) {
+            generate(L.jobs[r.job], r);
+        } else {
             // ray id outside the views: flag it, leave no stale values behind
             const float nan = __builtin_nanf("");
             if (L.flat.disp) L.flat.disp[2 * slot] = L.flat.disp[2 * slot + 1] = nan;
@@ -694,7 +709,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
         const uint32_t nidle = (uint32_t)__popcll(idle);
         if (!done) {
             if (fin >= 0) {
-                finish_ray<SCENE>(L, r, c, w, steps, fin, c, fin_surf, ntests);
+                finish_ray<SCENE>(L, L.jobs[r.job], r, c, w, steps, fin, c, fin_surf, ntests);
                 fin = -1;
             }
             if (next == end) {
@@ -759,7 +774,7 @@ __device__ __forceinline__ void march(const TraceLaunch &L)
             }
         }
         if (done && __ballot(active) == 0ull) {
-            if (fin >= 0) finish_ray<SCENE>(L, r, c, w, steps, fin, c, fin_surf, ntests);
+            if (fin >= 0) finish_ray<SCENE>(L, L.jobs[r.job], r, c, w, steps, fin, c, fin_surf, ntests);
             break;
         }
         // once nothing is left to hand out, step until every lane is done
@@ -968,11 +983,11 @@ hipError_t launch_raygen(const TraceLaunch &L, bool clear_counters, hipStream_t 
     const dim3 g((unsigned)((L.nslots + kRaygenBlock - 1) / kRaygenBlock));
     hipEvent_t e0 = clear_counters ? nullptr : t.start;
     if (L.mesh.ntris > 0)
-        hipExtLaunchKernelGGL(k_raygen<3>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
+        hipExtLaunchKernelGGL(k_raygen<3>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L, L.jobs);
     else if (L.nquads > 0)
-        hipExtLaunchKernelGGL(k_raygen<1>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
+        hipExtLaunchKernelGGL(k_raygen<1>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L, L.jobs);
     else
-        hipExtLaunchKernelGGL(k_raygen<0>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L);
+        hipExtLaunchKernelGGL(k_raygen<0>, g, dim3(kRaygenBlock), 0, s, e0, nullptr, 0, L, L.jobs);
     hipExtLaunchKernelGGL(k_raygen_place, g, dim3(kRaygenBlock), 0, s, nullptr, t.stop, 0, L);
     return hipGetLastError();
 }
