@@ -67,7 +67,10 @@ def _default(ctx):
                                         (3, (40, 33, 19), 0.02),
                                         # z reach (cell + 4h) shorter than a brick: cell rows whose reach
                                         # cuts the brick at both ends (full loop) or misses it
-                                        (4, (24, 20, 10), 0.012)])
+                                        (4, (24, 20, 10), 0.012),
+                                        # z spacing 4-5x the x-y spacing: the support spans about one plane
+                                        # either side, and the default brick depth is 4
+                                        (5, (40, 40, 6), 0.03)])
 def test_splat_parity_small(ctx, haze, seed, res, h, method):
     _use(ctx, method)
     try:
