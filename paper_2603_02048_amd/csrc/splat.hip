@@ -779,11 +779,18 @@ __device__ __forceinline__ float central(float fm, float c, float fp, int32_t id
 template <int DT>
 __global__ __launch_bounds__(256) void k_grad_pack(const float *__restrict__ dn, int32_t dsx, int32_t dsy,
                                                    int32_t dsz, int32_t rx, int32_t ry, int32_t rz, float ix,
-                                                   float iy, float iz, float scale, void *__restrict__ out)
+                                                   float iy, float iz, float scale, int32_t gz, int32_t gx,
+                                                   int32_t nblocks, int32_t per_xcd, void *__restrict__ out)
 {
-    const int32_t k = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x & 63);
-    const int32_t i = (int32_t)blockIdx.y * 4 + (int32_t)(threadIdx.x >> 6);
-    const int32_t j0 = (int32_t)blockIdx.z * GP_Y;
+    // blocks (z, x, y) in that order, each XCD (workgroups are dealt
+    // round-robin over the 8 XCDs) taking a contiguous run of them, so that
+    // the neighbouring columns a block reads mostly sit in the same L2
+    const int32_t blk = (int32_t)(blockIdx.x & 7u) * per_xcd + (int32_t)(blockIdx.x >> 3);
+    if (blk >= nblocks) return;
+    const int32_t bz = blk % gz, bx = (blk / gz) % gx, by = blk / (gz * gx);
+    const int32_t k = bz * 64 + (int32_t)(threadIdx.x & 63);
+    const int32_t i = bx * 4 + (int32_t)(threadIdx.x >> 6);
+    const int32_t j0 = by * GP_Y;
     if (k >= rz || i >= rx) return;
     // voxel counts are below 2^31 (checked on the host): 32-bit index math
     int32_t u = i * dsx + j0 * dsy + k * dsz;    // delta_n
@@ -935,19 +942,20 @@ hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float
 hipError_t launch_grad_pack(int dtype, const float *dn, bool dn_zfast, const int32_t res[3], const float inv_sp[3],
                             float scale, void *out, hipStream_t s, const KTimer &t)
 {
-    const dim3 g((unsigned)((res[2] + 63) / 64), (unsigned)((res[0] + 3) / 4), (unsigned)((res[1] + GP_Y - 1) / GP_Y)),
-        b(256);
+    const int32_t gz = (res[2] + 63) / 64, gx = (res[0] + 3) / 4, gy = (res[1] + GP_Y - 1) / GP_Y;
+    const int32_t nblocks = gz * gx * gy, per_xcd = (nblocks + 7) / 8;
+    const dim3 g((unsigned)(per_xcd * 8)), b(256);
     const int32_t dsx = dn_zfast ? res[2] : 1, dsy = dn_zfast ? res[0] * res[2] : res[0],
                   dsz = dn_zfast ? 1 : res[0] * res[1];
     if (dtype == DT_F32)
         hipExtLaunchKernelGGL(k_grad_pack<DT_F32>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0], res[1],
-                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, gz, gx, nblocks, per_xcd, out);
     else if (dtype == DT_F16)
         hipExtLaunchKernelGGL(k_grad_pack<DT_F16>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0], res[1],
-                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+                              res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, gz, gx, nblocks, per_xcd, out);
     else
         hipExtLaunchKernelGGL(k_grad_pack<DT_BF16>, g, b, 0, s, t.start, t.stop, 0, dn, dsx, dsy, dsz, res[0],
-                              res[1], res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, out);
+                              res[1], res[2], inv_sp[0], inv_sp[1], inv_sp[2], scale, gz, gx, nblocks, per_xcd, out);
     return hipGetLastError();
 }
 
