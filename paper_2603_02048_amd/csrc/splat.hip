@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
                                                     uint32_t *__restrict__ lrank, uint32_t *__restrict__ count,
                                                     uint32_t *__restrict__ mmax, uint32_t *__restrict__ fail)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // 64-bit: the last workgroup reaches past 2^31 - 1 when n is near it
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the call's scan-failure word starts clear (the scan runs after this launch)
     if (i == 0) *fail = 0u;
     uint32_t mbits = 0u;
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ start,
                                                       uint32_t *__restrict__ slots, const uint32_t *__restrict__ fail)
 {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || *fail) return;
     uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     float4 *__restrict__ sorted, const uint32_t *__restrict__ fail)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || *fail) return;
     const uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
