@@ -211,7 +211,8 @@ hz_status hz_field_info(const hz_field *field, hz_grid *grid, hz_dtype *dtype, f
  * context's pool and is reused (by a later field of the same size) only by
  * work ordered after every launch already queued that reads the field.
  * Pooled memory stays charged to the budget until the context needs the room
- * or is destroyed. */
+ * or is destroyed.  Errors: HZ_E_INVALID (NULL arguments, unknown field, or a
+ * request still waiting in the serving loop reads the field). */
 hz_status hz_field_release(hz_ctx *ctx, hz_field *field);
 
 /* ---------------------------------------------------------------------- */
@@ -383,7 +384,9 @@ hz_status hz_mesh_create(hz_ctx *ctx, const hz_triangle *tris, int32_t ntris, co
 hz_status hz_mesh_info(const hz_mesh *mesh, int32_t *ntris, int32_t shell_res[3], float *shell_cell,
                        int64_t *list_entries, uint64_t *bytes);
 
-/* Release a mesh; waits for the traces that use it. */
+/* Release a mesh; waits for the traces that use it.  Errors: HZ_E_INVALID
+ * (NULL arguments, a mesh of another context, or a request still waiting in
+ * the serving loop reads the mesh). */
 hz_status hz_mesh_release(hz_ctx *ctx, hz_mesh *mesh);
 
 /* hz_trace_scene with a triangle mesh instead of boards.  The first triangle
@@ -455,8 +458,9 @@ hz_status hz_server_start(hz_ctx *ctx, int32_t slots, int64_t max_batch_rays);
 
 /* Submit a request: trace all pixels of views[0..nviews) through `field` with
  * `step`.  Non-blocking; views and step are copied.  The library allocates
- * the request's outputs (see hz_request_outputs); `field` must stay alive
- * until the request completes.  Requests that arrive while others run join
+ * the request's outputs (see hz_request_outputs).  hz_field_release refuses
+ * `field` while the request waits to be launched; once it is launched, a
+ * release of the field defers its reuse past the request's work.  Requests that arrive while others run join
  * the next launch whose slot and memory are free; requests for different
  * fields of the same grid and storage type share launches.
  * Errors: HZ_E_INVALID (as hz_trace_views, or no server), HZ_E_BUDGET (the
@@ -472,8 +476,9 @@ hz_status hz_submit_scene(hz_ctx *ctx, const hz_field *field, const hz_view *vie
                           const hz_scene *scene, const hz_step *step, hz_ticket *out);
 
 /* hz_submit with a triangle mesh (as hz_trace_mesh, without tri_tests; the
- * request's surface array reports the mesh surfaces).  `mesh` must stay alive
- * until the request completes.  Only requests with the same mesh (and grid,
+ * request's surface array reports the mesh surfaces).  hz_mesh_release refuses
+ * `mesh` while the request waits to be launched, and waits for its work once
+ * it is launched.  Only requests with the same mesh (and grid,
  * storage type and step control) share a launch.  Errors: as hz_submit, and
  * HZ_E_INVALID for a NULL mesh, a mesh of another context, or steps longer
  * than the mesh's reach. */

@@ -367,6 +367,8 @@ extern "C" hz_status hz_mesh_release(hz_ctx *c, hz_mesh *m)
 {
     if (!c || !m) return set_error(HZ_E_INVALID, "hz_mesh_release: NULL argument");
     if (m->ctx != c) return set_error(HZ_E_INVALID, "hz_mesh_release: mesh belongs to another context");
+    if (server_waiting_use(c, nullptr, m))
+        return set_error(HZ_E_INVALID, "hz_mesh_release: a request waiting in the serving loop reads the mesh");
     (void)hipSetDevice(ctx_device(c));
     for (const CallMark &t : m->uses) (void)ctx_mark_sync(c, t);
     ctx_free(c, m->mem, m->bytes);

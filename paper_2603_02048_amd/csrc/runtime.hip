@@ -989,6 +989,8 @@ extern "C" hz_status hz_field_info(const hz_field *f, hz_grid *grid, hz_dtype *d
 extern "C" hz_status hz_field_release(hz_ctx *c, hz_field *f)
 {
     if (!c || !f) return fail(HZ_E_INVALID, "hz_field_release: NULL argument");
+    if (server_waiting_use(c, f, nullptr))
+        return fail(HZ_E_INVALID, "hz_field_release: a request waiting in the serving loop reads the field");
     {
         std::lock_guard<std::mutex> g(c->fields_mu);
         auto it = std::find(c->fields.begin(), c->fields.end(), f);

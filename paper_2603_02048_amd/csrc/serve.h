@@ -9,6 +9,7 @@
 namespace haze {
 struct Server;
 void server_destroy(Server *s);
+bool server_waiting_use(hz_ctx *c, const hz_field *f, const hz_mesh *m);   // a queued request reads f or m
 
 // context/field accessors implemented in runtime.hip
 hz_status ctx_alloc(hz_ctx *c, void **p, size_t bytes);

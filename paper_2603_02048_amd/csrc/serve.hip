@@ -106,6 +106,19 @@ struct Server {
     size_t trim_fields = 0;            // bytes of pooled (released) field memory to give back, unlocked
 };
 
+// Whether a request still waiting in the serving loop (not yet launched: a
+// launched one has left its completion mark on the field and the mesh) reads
+// field f or mesh m.
+bool server_waiting_use(hz_ctx *c, const hz_field *f, const hz_mesh *m)
+{
+    Server *S = ctx_server(c);
+    if (!S) return false;
+    std::lock_guard<std::mutex> g(S->mu);
+    for (const Request *r : S->pending)
+        if ((f && r->field == f) || (m && r->mesh == m)) return true;
+    return false;
+}
+
 static double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();

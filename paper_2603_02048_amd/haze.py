@@ -472,7 +472,8 @@ class Context:
 
     def submit(self, field: Field, views: Sequence, step, quads=None, mesh: Optional[Mesh] = None) -> int:
         """Submit a request (with scene boards `quads`, (K, 3, 3), or a Mesh,
-        if given; the mesh must stay alive until the request completes)."""
+        if given).  Releasing the field or mesh fails while the request waits
+        to be launched."""
         t = C.c_uint64()
         if mesh is not None:
             if quads is not None:

@@ -139,6 +139,54 @@ def test_serve_budget_admission_and_errors(haze):
         ctx.close()
 
 
+def test_serve_release_refused_while_waiting(haze):
+    """hz_field_release and hz_mesh_release refuse a field or mesh that a
+    request still waiting in the serving loop reads (HZ_E_INVALID), and both
+    succeed once the request has run.  The request is held back by the HBM
+    budget: an earlier request's outputs occupy it until released."""
+    from tests.test_gpu_scene import _boards
+    print("case serve release while waiting: 256x128 mesh requests, one slot", flush=True)
+    wl = W.make_small(seed=3, n=3000, width=8, height=8, nviews=1)
+    st = wl.step_adaptive
+    views = [W.ring_view(wl.grid.lo, wl.grid.hi, 0.3, 1.2, 256, 128)]
+    tris = W.tessellate_quads(_boards(wl.grid.lo, wl.grid.hi), 2)
+    per_req = 256 * 128 * 38          # the request's outputs, its surface array included
+    max_batch = 256 * 128
+    probe = haze.Context(0)
+    f0 = probe.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
+    m0 = probe.mesh_create(*tris, reach=st.ds_max)
+    used, _ = probe.memory()
+    probe.close()
+    budget = used + 5 * max_batch + 2 * 65 * 256 + 64 * 1024 + int(1.5 * per_req)
+    ctx = haze.Context(0, budget_bytes=budget)
+    try:
+        f = ctx.splat_index_field(haze.upload_particles(wl.particles), wl.grid, wl.k_gd, wl.h)
+        m = ctx.mesh_create(*tris, reach=st.ds_max)
+        ctx.server_start(slots=1, max_batch_rays=max_batch)
+        t0 = ctx.submit(f, views, st, mesh=m)
+        _wait(ctx, [t0])
+        t1 = ctx.submit(f, views, st, mesh=m)
+        time.sleep(0.05)
+        assert ctx.poll(t1) is None                     # waits for output memory
+        for obj in (f, m):
+            with pytest.raises(haze.HazeError) as e:
+                obj.release()
+            assert e.value.status == haze.E_INVALID
+            assert obj.handle
+        first = to_np(ctx.request_outputs(t0))
+        ctx.request_release(t0)
+        _wait(ctx, [t1])
+        second = to_np(ctx.request_outputs(t1))
+        for k in first:
+            assert np.array_equal(first[k].view(np.uint8), second[k].view(np.uint8)), k
+        m.release()                                     # launched: waits for its work
+        f.release()
+        ctx.request_release(t1)
+        ctx.server_stop()
+    finally:
+        ctx.close()
+
+
 def test_serve_slots_overlap_on_device(haze):
     """Batches on two slots run at the same time on the device: requests for
     fields of different grids cannot share a launch, so each pair goes to two
