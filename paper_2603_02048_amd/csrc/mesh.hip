@@ -370,7 +370,12 @@ extern "C" hz_status hz_mesh_release(hz_ctx *c, hz_mesh *m)
     if (server_waiting_use(c, nullptr, m))
         return set_error(HZ_E_INVALID, "hz_mesh_release: a request waiting in the serving loop reads the mesh");
     (void)hipSetDevice(ctx_device(c));
-    for (const CallMark &t : m->uses) (void)ctx_mark_sync(c, t);
+    std::vector<CallMark> uses;
+    {
+        std::lock_guard<std::mutex> g(m->mu);
+        uses = m->uses;
+    }
+    for (const CallMark &t : uses) (void)ctx_mark_sync(c, t);
     ctx_free(c, m->mem, m->bytes);
     delete m;
     return HZ_OK;
