@@ -431,7 +431,12 @@ static hz_status check_field_usable(hz_ctx *c, const hz_field *f, const char *fn
 
 static void field_destroy(hz_field *f)
 {
-    for (const CallMark &t : f->uses) (void)mark_sync(f->ctx, t);
+    std::vector<CallMark> uses;
+    {
+        std::lock_guard<std::mutex> g(f->mu);
+        uses = f->uses;
+    }
+    for (const CallMark &t : uses) (void)mark_sync(f->ctx, t);
     if (f->data) ctx_free(f->ctx, f->data, f->bytes);
     delete f;
 }
@@ -441,13 +446,18 @@ static void field_destroy(hz_field *f)
 static void field_recycle(hz_field *f)
 {
     hz_ctx *c = f->ctx;
-    if (f->uses.empty()) {
+    std::vector<CallMark> uses;
+    {
+        std::lock_guard<std::mutex> g(f->mu);
+        uses.swap(f->uses);
+    }
+    if (uses.empty()) {
         field_destroy(f);
         return;
     }
     {
         std::lock_guard<std::mutex> g(c->pool_mu);
-        c->pool.push_back({f->data, (size_t)f->bytes, std::move(f->uses)});
+        c->pool.push_back({f->data, (size_t)f->bytes, std::move(uses)});
     }
     delete f;
 }
