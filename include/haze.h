@@ -118,6 +118,11 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *   "splat.brick_z"        gather brick depth BZ: 4 or 8 voxels, 0 = the one
  *                          that brings the brick closer to twice as deep as
  *                          wide (default 0)
+ *   "splat.order"          1: the gather hands out its bricks heaviest first,
+ *                          by each brick's candidate count in the context's
+ *                          previous gather over the same bricks (up to 8,192
+ *                          bricks); 0: in index order.  The field is the same
+ *                          bits either way (default 1)
  *   "splat.scan_fault_test" 1: the next splat calls' one-pass cell-list scans
  *                          wait for tile sums that never come, with a short
  *                          bound, so that the failure path runs (default 0;

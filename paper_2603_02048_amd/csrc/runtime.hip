@@ -24,13 +24,14 @@
 namespace haze {
 hipError_t launch_cell_list(const float *, const float *, const float *, const float *, int32_t, const CellGrid &,
                             uint32_t *, uint32_t *, int64_t, uint32_t *, uint32_t *, uint32_t *, float4 *, void *,
-                            bool, uint32_t *, bool, const ScanGuard &, hipStream_t, const KTimer &);
+                            bool, uint32_t *, bool, const ScanGuard &, uint32_t *, int32_t, bool, hipStream_t,
+                            const KTimer &);
 int32_t scan_tiles(int32_t ncells);
 size_t scan_scratch_bytes(int32_t ncells);
 bool scan_is_onepass(int32_t ncells);
 uint32_t *scan_fail_word(void *scan);
-hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, const uint32_t *, hipStream_t,
-                        const KTimer &);
+hipError_t launch_splat(const SplatParams &, const uint32_t *, const float4 *, float *, const uint32_t *, uint32_t *,
+                        const uint32_t *, hipStream_t, const KTimer &);
 hipError_t launch_splat_scatter(const SplatParams &, const uint32_t *, const float4 *, const uint32_t *, float *,
                                 const uint32_t *, hipStream_t, const KTimer &);
 int scatter_max_rows(const SplatParams &P);
@@ -101,6 +102,10 @@ struct PinnedSlot {
 
 // Events of the completion marks (a ring; see mark_issue).
 constexpr uint64_t kMarkRing = 64;
+// largest brick count the gather dispatches by weight: the ordering runs in
+// one workgroup of the cell-count kernel, which it outlasts beyond this (at
+// 32,768 bricks it cost more than the 1% the order gained the splat)
+constexpr int32_t kMaxOrderedBricks = 8192;
 
 struct hz_field {
     hz_ctx *ctx = nullptr;
@@ -125,6 +130,11 @@ struct hz_ctx {
     // splat scratch; `count` is clean when all zero, `tiles` when the one-pass
     // scan's ticket counter equals scan_base and its tags are older
     Scratch cid, count, start, lrank, slots, sorted, dn, tiles;
+    // the gather's per-brick candidate counts, dispatch order and largest
+    // count; `clean` while the counts belong to the bricks in brick_dims
+    // (from the last gather, which issued all its launches)
+    Scratch bricks;
+    int32_t brick_dims[4] = {0, 0, 0, 0};
     uint32_t scan_base = 0;
     // trace scratch; `counters` holds two counter sets used alternately,
     // counter_set the one the next launch uses
@@ -142,6 +152,7 @@ struct hz_ctx {
     int32_t blocks_per_cu = 0;   // 0: as many as fit
     int32_t splat_method = 0;    // 0: auto, 1: gather, 2: scatter
     int32_t splat_brick_z = 0;   // gather brick depth: 0 auto, 4 or 8
+    int32_t splat_order = 1;     // gather bricks heaviest first (by the previous gather's counts)
     int32_t scan_fault_test = 0; // 1: the one-pass scan's waits give up (fault test)
     // host-visible word (pinned, device-mapped) where a failed scan leaves
     // the serial number of its splat call; splat calls are numbered from 1
@@ -607,8 +618,8 @@ extern "C" void hz_ctx_destroy(hz_ctx *c)
         for (hipEvent_t e : c->prof_free) (void)hipEventDestroy(e);
         c->prof_free.clear();
     }
-    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->lrank, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->jobs,
-                       &c->hits, &c->bins, &c->counters})
+    for (Scratch *s : {&c->cid, &c->count, &c->start, &c->lrank, &c->slots, &c->sorted, &c->dn, &c->tiles, &c->bricks,
+                       &c->jobs, &c->hits, &c->bins, &c->counters})
         scratch_free(c, *s);
     for (PinnedSlot &p : c->pinned) {
         (void)mark_sync(c, p.last);
@@ -634,6 +645,9 @@ extern "C" hz_status hz_ctx_tune(hz_ctx *c, const char *key, int64_t value)
         if (value != 0 && value != 4 && value != 8)
             return fail(HZ_E_INVALID, "hz_ctx_tune: splat.brick_z must be 0, 4 or 8");
         c->splat_brick_z = (int32_t)value;
+    } else if (k == "splat.order") {
+        if (value < 0 || value > 1) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.order must be 0 or 1");
+        c->splat_order = (int32_t)value;
     } else if (k == "splat.method") {
         if (value < 0 || value > 2) return fail(HZ_E_INVALID, "hz_ctx_tune: splat.method must be 0, 1 or 2");
         c->splat_method = (int32_t)value;
@@ -869,6 +883,24 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     const bool scatter = c->splat_method == 2;
     if (scatter && scatter_max_rows(sp) > scatter_rows_limit())
         return fail(HZ_E_UNSUPPORTED, "%s: h too large for the scatter splat's tile (use splat.method 1)", fn);
+    // Up to kMaxOrderedBricks bricks, the gather records each brick's
+    // candidate count, and the next gather over the same bricks dispatches
+    // them heaviest first (the order is computed by the cell-count kernel's
+    // first workgroup).
+    const int32_t nbricks = sp.nbx * sp.nby * sp.nbz;
+    uint32_t *bwork = nullptr, *border = nullptr;
+    bool ordered = false;
+    const bool record = !scatter && nbricks <= kMaxOrderedBricks;
+    if (record) {
+        const bool same = c->brick_dims[0] == sp.nbx && c->brick_dims[1] == sp.nby && c->brick_dims[2] == sp.nbz &&
+                          c->brick_dims[3] == sp.bz;
+        st = scratch_acquire(c, c->bricks, 8u * (size_t)nbricks + 4u, s);
+        if (st != HZ_OK) return st;
+        bwork = (uint32_t *)c->bricks.ptr;
+        border = bwork + nbricks;
+        ordered = c->splat_order && same && c->bricks.clean;
+        c->bricks.clean = false;   // until this call's launches are issued
+    }
     hz_field *f = nullptr;
     st = new_field(c, g, prm->dtype, prm->store_scale, s, &f);
     if (st != HZ_OK) return st;
@@ -896,7 +928,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     hipError_t e = launch_cell_list(P->x, P->y, P->z, P->m, n, cg, (uint32_t *)c->cid.ptr, (uint32_t *)c->count.ptr,
                                     clear_words, (uint32_t *)c->start.ptr, (uint32_t *)c->lrank.ptr,
                                     (uint32_t *)c->slots.ptr, (float4 *)c->sorted.ptr, c->tiles.ptr, scan_reset,
-                                    &c->scan_base, scatter, guard, s, t0);
+                                    &c->scan_base, scatter, guard, bwork, nbricks, ordered, s, t0);
     prof_commit(c, "cell_list", t0);
     if (e == hipSuccess) {
         c->count.clean = !scatter;
@@ -911,7 +943,7 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
                                      t1);
         else
             e = launch_splat(sp, (const uint32_t *)c->start.ptr, (const float4 *)c->sorted.ptr, (float *)c->dn.ptr,
-                             fail_word, s, t1);
+                             fail_word, bwork, ordered ? border : nullptr, s, t1);
         prof_commit(c, "splat", t1);
     }
     if (e != hipSuccess) {
@@ -930,6 +962,14 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         return st;
     }
     for (int i = 0; i < 8; ++i) bufs[i]->last = done;
+    if (record) {
+        c->bricks.last = done;
+        c->bricks.clean = true;
+        c->brick_dims[0] = sp.nbx;
+        c->brick_dims[1] = sp.nby;
+        c->brick_dims[2] = sp.nbz;
+        c->brick_dims[3] = sp.bz;
+    }
     field_mark_made(f, done);
     register_field(c, f);
     *out = f;

@@ -7,7 +7,8 @@
 //
 // Pipeline (all integer work exact, so the result is bitwise repeatable):
 //   k_cell_count   particle -> cell id (cells of edge h over the grid box grown
-//                  by 2h), integer histogram with atomics
+//                  by 2h), integer histogram with atomics; one more workgroup
+//                  orders the gather's bricks heaviest first (order_bricks)
 //   k_scan_onepass exclusive prefix sum of the histogram in one launch
 //                  (tile sums published with tickets, lower tiles added);
 //                  k_scan_* in three passes for very large cell counts
@@ -15,7 +16,8 @@
 //                  the histogram atomics: an arbitrary order inside the cell)
 //   k_cell_order   per particle, its rank by index among its cell's members
 //                  (stable order); (x, y, z, m) into cell-sorted float4 records
-//   k_splat        one workgroup per 8x8x4 or 8x8x8 voxel brick, its cell-list
+//   k_splat        one workgroup per 8x8x4 or 8x8x8 voxel brick (records the
+//                  brick's candidate count for the next call's order), its cell-list
 //                  rows dealt to four waves: every lane owns a column of
 //                  voxels; each candidate particle is culled to the planes
 //                  it reaches (64 candidates at a time, one per lane), then
@@ -47,6 +49,71 @@ __device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, in
     return (int)c;
 }
 
+// Dispatch order of the gather's bricks, heaviest first.  bwork[b] is the
+// number of candidate particles brick b had in the previous gather over the
+// same bricks, bwork[2 nb] their largest; the bricks are bucketed by that
+// count into kOrderBuckets buckets of equal width below the largest, and
+// border[] (= bwork + nb) lists them bucket by bucket, heaviest bucket first
+// (in any order inside a bucket).  Every brick sums in its own fixed order, so
+// the field does not depend on the order; handing the heavy bricks out first
+// shortens the launch's tail.  One 256-thread workgroup; both passes read the
+// same counts, so the placement is a permutation of [0, nb).  Clears the
+// largest count for the gather that follows.
+constexpr int kOrderBuckets = 64;   // one per lane of the scan below
+constexpr int kOrderUnroll = 16;
+__device__ void order_bricks(uint32_t *__restrict__ bwork, int32_t nb, bool order)
+{
+    __shared__ uint32_t hist[kOrderBuckets], cur[kOrderBuckets];
+    uint32_t *border = bwork + nb, *bmax = bwork + 2 * (size_t)nb;
+    if (!order) {
+        if (threadIdx.x == 0) *bmax = 0u;
+        return;
+    }
+    // buckets per count (a float scale: an integer division per brick would
+    // cost more than the whole ordering)
+    const float scale = (float)kOrderBuckets / ((float)*bmax + 1.0f);
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+    __syncthreads();   // every thread has read the largest count
+    if (threadIdx.x == 0) *bmax = 0u;
+    const auto bucket = [&](uint32_t w) -> uint32_t {
+        return (uint32_t)(kOrderBuckets - 1) - min((uint32_t)(kOrderBuckets - 1), (uint32_t)((float)w * scale));
+    };
+    // Each thread takes a contiguous run of bricks, kOrderUnroll counts in
+    // flight per round: the lanes of one LDS atomic then hold bricks far apart,
+    // whose buckets mostly differ (neighbouring bricks, which mostly share a
+    // bucket, would serialise the atomic on one address).
+    const int32_t per = (nb + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t mine0 = (int32_t)threadIdx.x * per, mine1 = min(nb, mine0 + per);
+    for (int32_t b0 = mine0; b0 < mine1; b0 += kOrderUnroll) {
+        uint32_t w[kOrderUnroll];
+#pragma unroll
+        for (int u = 0; u < kOrderUnroll; ++u) w[u] = b0 + u < mine1 ? bwork[b0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kOrderUnroll; ++u)
+            if (b0 + u < mine1) atomicAdd(&hist[bucket(w[u])], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {   // exclusive scan of the 64 bucket sizes, one per lane
+        const uint32_t h = hist[threadIdx.x];
+        uint32_t incl = h;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)incl, off);
+            if ((int)threadIdx.x >= off) incl += o;
+        }
+        cur[threadIdx.x] = incl - h;
+    }
+    __syncthreads();
+    for (int32_t b0 = mine0; b0 < mine1; b0 += kOrderUnroll) {
+        uint32_t w[kOrderUnroll];
+#pragma unroll
+        for (int u = 0; u < kOrderUnroll; ++u) w[u] = b0 + u < mine1 ? bwork[b0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kOrderUnroll; ++u)
+            if (b0 + u < mine1) border[atomicAdd(&cur[bucket(w[u])], 1u)] = (uint32_t)(b0 + u);
+    }
+}
+
 // Particle -> cell id (0xffffffff when outside the grown box) + histogram;
 // the atomic's old value is the particle's arrival rank in its cell (an
 // arbitrary order that k_cell_order replaces by index order).  With MMAX,
@@ -59,10 +126,23 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
                                                     const float *__restrict__ z, const float *__restrict__ m,
                                                     int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
                                                     uint32_t *__restrict__ lrank, uint32_t *__restrict__ count,
-                                                    uint32_t *__restrict__ mmax, uint32_t *__restrict__ fail)
+                                                    uint32_t *__restrict__ mmax, uint32_t *__restrict__ fail,
+                                                    uint32_t *__restrict__ bwork, int32_t nbricks,
+                                                    int32_t order)
 {
+    // With bwork, workgroup 0 computes the gather's brick order for this call
+    // from the previous gather's counts, beside the binning of the others
+    // (which start one workgroup later).
+    uint32_t block = blockIdx.x;
+    if (bwork) {
+        if (block == 0u) {
+            order_bricks(bwork, nbricks, order != 0);
+            return;
+        }
+        --block;
+    }
     // 64-bit: the last workgroup reaches past 2^31 - 1 when n is near it
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)block * blockDim.x + threadIdx.x;
     // the call's scan-failure word starts clear (the scan runs after this launch)
     if (i == 0) *fail = 0u;
     uint32_t mbits = 0u;
@@ -388,15 +468,23 @@ template <int BZ>
 __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const uint32_t *__restrict__ start,
                                                             const float4 *__restrict__ parts, int32_t nbricks,
                                                             float *__restrict__ dn,
-                                                            const uint32_t *__restrict__ fail)
+                                                            const uint32_t *__restrict__ fail,
+                                                            uint32_t *__restrict__ bwork,
+                                                            const uint32_t *__restrict__ border)
 {
     __shared__ float partial[SPLAT_WAVES - 1][BZ][64];
+    __shared__ uint32_t wcand[SPLAT_WAVES];
     // per wave and culled candidate: z_v - z_j for the brick's planes (the
     // same for every lane), read back as a broadcast instead of one
     // subtraction per lane and plane
     __shared__ float4 dzs[SPLAT_WAVES][64][BZ / 4];
-    const int32_t brick = (int32_t)blockIdx.x;
-    if (brick >= nbricks) return;   // uniform over the workgroup
+    if ((int32_t)blockIdx.x >= nbricks) return;   // uniform over the workgroup
+    // the brick of this dispatch slot (heaviest first when an order is given)
+    int32_t brick = (int32_t)blockIdx.x;
+    if (border) {
+        const uint32_t o = __builtin_amdgcn_readfirstlane(border[blockIdx.x]);
+        if (o < (uint32_t)nbricks) brick = (int32_t)o;
+    }
     const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int32_t bx = brick % P.nbx;
@@ -450,6 +538,7 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
     const bool bad = *fail != 0u;
     int kz = ny >= 1 && !bad ? cz0 : cz1 + 1, ky = cy0 + wave;
     uint32_t c0 = 0u, s1 = 0u;   // the next candidate to cull; the row's end
+    uint32_t cand = 0u;          // candidates of this wave's rows (the next call's brick order)
     // moves to the next row; false when there is none
     const auto next_row = [&]() -> bool {
         // (wrapping past the y range without a loop)
@@ -476,6 +565,7 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
             const int row = (kz * cg.nc[1] + kyr) * cg.nc[0];
             c0 = __builtin_amdgcn_readfirstlane(start[row + kx0]);
             s1 = __builtin_amdgcn_readfirstlane(start[row + kx1 + 1]);
+            cand += s1 - c0;
         }
         return true;
     };
@@ -538,7 +628,15 @@ __global__ __launch_bounds__(64 * SPLAT_WAVES) void k_splat(SplatParams P, const
 #pragma unroll
         for (int v = 0; v < BZ; ++v) partial[wave - 1][v][lane] = part[v];
     }
+    if (lane == 0) wcand[wave] = cand;
     __syncthreads();
+    if (bwork && threadIdx.x == 0) {
+        uint32_t total = 0u;
+#pragma unroll
+        for (int w = 0; w < SPLAT_WAVES; ++w) total += wcand[w];
+        bwork[brick] = total;
+        atomicMax(bwork + 2 * (size_t)nbricks, total);
+    }
     if (wave == 0 && vx < P.res[0] && vy < P.res[1]) {
         const float sc = bad ? __builtin_nanf("") : P.scale;
 #pragma unroll
@@ -870,7 +968,7 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
                             const CellGrid &cg, uint32_t *cid, uint32_t *count, int64_t count_clear_words,
                             uint32_t *start, uint32_t *lrank, uint32_t *slots, float4 *sorted, void *scan,
                             bool scan_reset, uint32_t *scan_base, bool want_mmax, const ScanGuard &guard,
-                            hipStream_t s, const KTimer &t)
+                            uint32_t *bwork, int32_t nbricks, bool order, hipStream_t s, const KTimer &t)
 {
     // The counts must start at zero; each scan leaves them so.
     // count[ncells+1] holds max |m| (scatter splat only), which the caller
@@ -898,11 +996,11 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     if (want_mmax)
         hipExtLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1, fail);
+                              count + cg.ncells + 1, fail, nullptr, 0, 0);
     else
-        hipExtLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
+        hipExtLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256) + (bwork ? 1 : 0)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1, fail);
+                              count + cg.ncells + 1, fail, bwork, nbricks, order ? 1 : 0);
     if (onepass) {
         hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, ntiles,
                            (uint32_t *)scan, (uint64_t *)((char *)scan + SCAN_TAG_OFFSET), *scan_base, start,
@@ -924,17 +1022,21 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     return hipGetLastError();
 }
 
+// bwork (optional): receives each brick's candidate count (and their largest
+// at bwork[2 nbricks], which the cell-count kernel cleared); border
+// (optional): the dispatch order of the bricks.
 hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn,
-                        const uint32_t *fail, hipStream_t s, const KTimer &t)
+                        const uint32_t *fail, uint32_t *bwork, const uint32_t *border, hipStream_t s,
+                        const KTimer &t)
 {
     const int32_t nbricks = P.nbx * P.nby * P.nbz;
     const dim3 g((unsigned)nbricks), b(64 * SPLAT_WAVES);
     if (P.bz == 8)
         hipExtLaunchKernelGGL(k_splat<8>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, dn,
-                              fail);
+                              fail, bwork, border);
     else
         hipExtLaunchKernelGGL(k_splat<4>, g, b, 0, s, t.start, t.stop, 0, P, start, sorted, nbricks, dn,
-                              fail);
+                              fail, bwork, border);
     return hipGetLastError();
 }
 

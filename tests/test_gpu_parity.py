@@ -109,6 +109,42 @@ def test_splat_is_bitwise_repeatable(ctx, haze, method):
         _default(ctx)
 
 
+def test_splat_brick_order_keeps_the_field(ctx, haze):
+    """The gather hands out its bricks heaviest first, by each brick's
+    candidate count in the previous gather over the same bricks.  The field is
+    bitwise the same in plain order, on a context's first gather (no counts
+    yet), on the gathers after it, and after the grid changes (the counts of
+    other bricks are not used); the order is a permutation, so no brick is
+    lost or repeated."""
+    print("case splat brick order: config 1, then a small grid, orders off/on", flush=True)
+    wls = [W.make_config(1), W.make_small(seed=8, n=6000, res=(40, 24, 16))]
+    parts = [haze.upload_particles(w.particles) for w in wls]
+
+    def field(k):
+        f = ctx.splat_index_field(parts[k], wls[k].grid, wls[k].k_gd, wls[k].h)
+        out = _field_np(ctx, f)
+        f.release()
+        return out
+
+    try:
+        fresh = haze.Context(0)   # first gather of a context: no counts
+        try:
+            f = fresh.splat_index_field(parts[0], wls[0].grid, wls[0].k_gd, wls[0].h)
+            first = _field_np(fresh, f)
+            f.release()
+        finally:
+            fresh.close()
+        ctx.tune("splat.order", 0)
+        plain = [field(0), field(1)]
+        ctx.tune("splat.order", 1)
+        runs = [(0, field(0)), (0, field(0)), (1, field(1)), (1, field(1)), (0, field(0))]
+        for k, got in [(0, first)] + runs:
+            for x, y in zip(plain[k], got):
+                assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), k
+    finally:
+        ctx.tune("splat.order", 1)
+
+
 @pytest.mark.parametrize("method", ["gather", "gather8", "scatter"])
 def test_splat_skips_nonfinite_masses(ctx, haze, method):
     """Particles whose mass is NaN or infinite add nothing: the field with a
@@ -333,12 +369,12 @@ def test_trace_edge_cases(ctx, haze):
 def test_tune_keys_checked(ctx, haze):
     for key, bad in (("march.refill_min", 0), ("march.refill_min", 65), ("march.blocks_per_cu", -1),
                      ("march.blocks_per_cu", 65), ("splat.method", 3), ("splat.brick_z", 5), ("splat.brick_z", 16),
-                     ("no.such.key", 1)):
+                     ("splat.order", 2), ("splat.order", -1), ("no.such.key", 1)):
         with pytest.raises(haze.HazeError) as e:
             ctx.tune(key, bad)
         assert e.value.status == haze.E_INVALID, (key, bad)
     for key, good in (("march.refill_min", 32), ("march.blocks_per_cu", 0), ("splat.method", 0),
-                      ("splat.brick_z", 8), ("splat.brick_z", 0)):
+                      ("splat.brick_z", 8), ("splat.brick_z", 0), ("splat.order", 0), ("splat.order", 1)):
         ctx.tune(key, good)
 
 
