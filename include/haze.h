@@ -120,7 +120,7 @@ hz_status hz_ctx_memory(const hz_ctx *ctx, uint64_t *used_bytes, uint64_t *budge
  *                          wide (default 0)
  *   "splat.order"          1: the gather hands out its bricks heaviest first,
  *                          by each brick's candidate count in the context's
- *                          previous gather over the same bricks (up to 8,192
+ *                          previous gather over the same bricks (up to 65,536
  *                          bricks); 0: in index order.  The field is the same
  *                          bits either way (default 1)
  *   "splat.scan_fault_test" 1: the next splat calls' one-pass cell-list scans

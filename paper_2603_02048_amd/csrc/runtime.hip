@@ -102,10 +102,9 @@ struct PinnedSlot {
 
 // Events of the completion marks (a ring; see mark_issue).
 constexpr uint64_t kMarkRing = 64;
-// largest brick count the gather dispatches by weight: the ordering runs in
-// one workgroup of the cell-count kernel, which it outlasts beyond this (at
-// 32,768 bricks it cost more than the 1% the order gained the splat)
-constexpr int32_t kMaxOrderedBricks = 8192;
+// largest brick count the gather dispatches by weight (each phase of the
+// ordering runs in one workgroup beside a cell-list kernel)
+constexpr int32_t kMaxOrderedBricks = 1 << 16;
 
 struct hz_field {
     hz_ctx *ctx = nullptr;
@@ -885,8 +884,8 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
         return fail(HZ_E_UNSUPPORTED, "%s: h too large for the scatter splat's tile (use splat.method 1)", fn);
     // Up to kMaxOrderedBricks bricks, the gather records each brick's
     // candidate count, and the next gather over the same bricks dispatches
-    // them heaviest first (the order is computed by the cell-count kernel's
-    // first workgroup).
+    // them heaviest first (the order is computed by an extra workgroup of the
+    // cell-count launch and one of the cell-order launch).
     const int32_t nbricks = sp.nbx * sp.nby * sp.nbz;
     uint32_t *bwork = nullptr, *border = nullptr;
     bool ordered = false;
@@ -894,7 +893,8 @@ extern "C" hz_status hz_splat_index_field(hz_ctx *c, const hz_particles *P, cons
     if (record) {
         const bool same = c->brick_dims[0] == sp.nbx && c->brick_dims[1] == sp.nby && c->brick_dims[2] == sp.nbz &&
                           c->brick_dims[3] == sp.bz;
-        st = scratch_acquire(c, c->bricks, 8u * (size_t)nbricks + 4u, s);
+        // counts, order, largest count, scale, 64 bucket sizes
+        st = scratch_acquire(c, c->bricks, 8u * (size_t)nbricks + 4u * 66u, s);
         if (st != HZ_OK) return st;
         bwork = (uint32_t *)c->bricks.ptr;
         border = bwork + nbricks;

@@ -8,14 +8,16 @@
 // Pipeline (all integer work exact, so the result is bitwise repeatable):
 //   k_cell_count   particle -> cell id (cells of edge h over the grid box grown
 //                  by 2h), integer histogram with atomics; one more workgroup
-//                  orders the gather's bricks heaviest first (order_bricks)
+//                  buckets the gather's bricks by weight (order_bricks_count)
 //   k_scan_onepass exclusive prefix sum of the histogram in one launch
 //                  (tile sums published with tickets, lower tiles added);
 //                  k_scan_* in three passes for very large cell counts
 //   k_cell_scatter particle index -> its slot (cell start + arrival rank from
 //                  the histogram atomics: an arbitrary order inside the cell)
 //   k_cell_order   per particle, its rank by index among its cell's members
-//                  (stable order); (x, y, z, m) into cell-sorted float4 records
+//                  (stable order); (x, y, z, m) into cell-sorted float4 records;
+//                  one more workgroup lists the bricks heaviest first
+//                  (order_bricks_place)
 //   k_splat        one workgroup per 8x8x4 or 8x8x8 voxel brick (records the
 //                  brick's candidate count for the next call's order), its cell-list
 //                  rows dealt to four waves: every lane owns a column of
@@ -49,52 +51,84 @@ __device__ __forceinline__ int cell_coord(float x, float clo, float inv_cell, in
     return (int)c;
 }
 
-// Dispatch order of the gather's bricks, heaviest first.  bwork[b] is the
-// number of candidate particles brick b had in the previous gather over the
-// same bricks, bwork[2 nb] their largest; the bricks are bucketed by that
-// count into kOrderBuckets buckets of equal width below the largest, and
-// border[] (= bwork + nb) lists them bucket by bucket, heaviest bucket first
-// (in any order inside a bucket).  Every brick sums in its own fixed order, so
-// the field does not depend on the order; handing the heavy bricks out first
-// shortens the launch's tail.  One 256-thread workgroup; both passes read the
-// same counts, so the placement is a permutation of [0, nb).  Clears the
-// largest count for the gather that follows.
+// Dispatch order of the gather's bricks, heaviest first, in two phases that
+// each run in one extra 256-thread workgroup of a cell-list kernel, beside
+// that kernel's own work.  bwork[b] is the number of candidate particles
+// brick b had in the previous gather over the same bricks and bwork[2 nb]
+// their largest.  The bricks are bucketed by that count into kOrderBuckets
+// buckets of equal width below the largest; border[] (= bwork + nb) lists them
+// bucket by bucket, heaviest bucket first (in any order inside a bucket).
+// Every brick sums in its own fixed order, so the field does not depend on
+// the order; handing the heavy bricks out first shortens the launch's tail.
+// Both phases bucket the same counts with the same scale, so the placement is
+// a permutation of [0, nb).
 constexpr int kOrderBuckets = 64;   // one per lane of the scan below
 constexpr int kOrderUnroll = 16;
-__device__ void order_bricks(uint32_t *__restrict__ bwork, int32_t nb, bool order)
+struct BrickOrder {
+    uint32_t *work;    // [nb] counts, [nb] order, largest, scale (float bits), kOrderBuckets bucket sizes
+    int32_t nb;
+    int32_t order;     // 0: only clear the largest count for the gather that follows
+    __device__ uint32_t *border() const { return work + nb; }
+    __device__ uint32_t *bmax() const { return work + 2 * (size_t)nb; }
+    __device__ uint32_t *scale() const { return work + 2 * (size_t)nb + 1; }
+    __device__ uint32_t *hist() const { return work + 2 * (size_t)nb + 2; }
+};
+
+__device__ __forceinline__ uint32_t order_bucket(uint32_t w, float scale)
 {
-    __shared__ uint32_t hist[kOrderBuckets], cur[kOrderBuckets];
-    uint32_t *border = bwork + nb, *bmax = bwork + 2 * (size_t)nb;
-    if (!order) {
-        if (threadIdx.x == 0) *bmax = 0u;
-        return;
-    }
-    // buckets per count (a float scale: an integer division per brick would
-    // cost more than the whole ordering)
-    const float scale = (float)kOrderBuckets / ((float)*bmax + 1.0f);
-    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
-    __syncthreads();   // every thread has read the largest count
-    if (threadIdx.x == 0) *bmax = 0u;
-    const auto bucket = [&](uint32_t w) -> uint32_t {
-        return (uint32_t)(kOrderBuckets - 1) - min((uint32_t)(kOrderBuckets - 1), (uint32_t)((float)w * scale));
-    };
-    // Each thread takes a contiguous run of bricks, kOrderUnroll counts in
-    // flight per round: the lanes of one LDS atomic then hold bricks far apart,
-    // whose buckets mostly differ (neighbouring bricks, which mostly share a
-    // bucket, would serialise the atomic on one address).
+    return (uint32_t)(kOrderBuckets - 1) - min((uint32_t)(kOrderBuckets - 1), (uint32_t)((float)w * scale));
+}
+
+// Each thread takes a contiguous run of bricks, kOrderUnroll counts in flight
+// per round: the lanes of one LDS atomic then hold bricks far apart, whose
+// buckets mostly differ (neighbouring bricks, which mostly share a bucket,
+// would serialise the atomic on one address).
+template <typename F>
+__device__ __forceinline__ void for_my_bricks(const uint32_t *__restrict__ work, int32_t nb, F &&f)
+{
     const int32_t per = (nb + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
     const int32_t mine0 = (int32_t)threadIdx.x * per, mine1 = min(nb, mine0 + per);
     for (int32_t b0 = mine0; b0 < mine1; b0 += kOrderUnroll) {
         uint32_t w[kOrderUnroll];
 #pragma unroll
-        for (int u = 0; u < kOrderUnroll; ++u) w[u] = b0 + u < mine1 ? bwork[b0 + u] : 0u;
+        for (int u = 0; u < kOrderUnroll; ++u) w[u] = b0 + u < mine1 ? work[b0 + u] : 0u;
 #pragma unroll
         for (int u = 0; u < kOrderUnroll; ++u)
-            if (b0 + u < mine1) atomicAdd(&hist[bucket(w[u])], 1u);
+            if (b0 + u < mine1) f(b0 + u, w[u]);
     }
+}
+
+// Phase 1 (in the cell-count launch): the scale and the bucket sizes; clears
+// the largest count.
+__device__ void order_bricks_count(const BrickOrder &O)
+{
+    __shared__ uint32_t hist[kOrderBuckets];
+    if (!O.order) {
+        if (threadIdx.x == 0) *O.bmax() = 0u;
+        return;
+    }
+    // buckets per count (a float scale: an integer division per brick would
+    // cost more than the whole ordering)
+    const float scale = (float)kOrderBuckets / ((float)*O.bmax() + 1.0f);
+    if (threadIdx.x < kOrderBuckets) hist[threadIdx.x] = 0u;
+    __syncthreads();   // every thread has read the largest count
+    if (threadIdx.x == 0) {
+        *O.bmax() = 0u;
+        *O.scale() = __float_as_uint(scale);
+    }
+    for_my_bricks(O.work, O.nb, [&](int32_t, uint32_t w) { atomicAdd(&hist[order_bucket(w, scale)], 1u); });
     __syncthreads();
+    if (threadIdx.x < kOrderBuckets) O.hist()[threadIdx.x] = hist[threadIdx.x];
+}
+
+// Phase 2 (in the cell-order launch): bucket starts, then every brick to its
+// place.
+__device__ void order_bricks_place(const BrickOrder &O)
+{
+    __shared__ uint32_t cur[kOrderBuckets];
+    const float scale = __uint_as_float(*O.scale());
     if (threadIdx.x < 64) {   // exclusive scan of the 64 bucket sizes, one per lane
-        const uint32_t h = hist[threadIdx.x];
+        const uint32_t h = O.hist()[threadIdx.x];
         uint32_t incl = h;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -104,14 +138,10 @@ __device__ void order_bricks(uint32_t *__restrict__ bwork, int32_t nb, bool orde
         cur[threadIdx.x] = incl - h;
     }
     __syncthreads();
-    for (int32_t b0 = mine0; b0 < mine1; b0 += kOrderUnroll) {
-        uint32_t w[kOrderUnroll];
-#pragma unroll
-        for (int u = 0; u < kOrderUnroll; ++u) w[u] = b0 + u < mine1 ? bwork[b0 + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < kOrderUnroll; ++u)
-            if (b0 + u < mine1) border[atomicAdd(&cur[bucket(w[u])], 1u)] = (uint32_t)(b0 + u);
-    }
+    uint32_t *border = O.border();
+    for_my_bricks(O.work, O.nb, [&](int32_t b, uint32_t w) {
+        border[atomicAdd(&cur[order_bucket(w, scale)], 1u)] = (uint32_t)b;
+    });
 }
 
 // Particle -> cell id (0xffffffff when outside the grown box) + histogram;
@@ -127,16 +157,14 @@ __global__ __launch_bounds__(256) void k_cell_count(const float *__restrict__ x,
                                                     int32_t n, CellGrid cg, uint32_t *__restrict__ cid,
                                                     uint32_t *__restrict__ lrank, uint32_t *__restrict__ count,
                                                     uint32_t *__restrict__ mmax, uint32_t *__restrict__ fail,
-                                                    uint32_t *__restrict__ bwork, int32_t nbricks,
-                                                    int32_t order)
+                                                    BrickOrder O)
 {
-    // With bwork, workgroup 0 computes the gather's brick order for this call
-    // from the previous gather's counts, beside the binning of the others
-    // (which start one workgroup later).
+    // With brick counts, workgroup 0 runs the first phase of the gather's
+    // brick order beside the binning of the others (one workgroup later).
     uint32_t block = blockIdx.x;
-    if (bwork) {
+    if (O.work) {
         if (block == 0u) {
-            order_bricks(bwork, nbricks, order != 0);
+            order_bricks_count(O);
             return;
         }
         --block;
@@ -359,9 +387,20 @@ __global__ __launch_bounds__(256) void k_cell_order(const uint32_t *__restrict__
                                                     const uint32_t *__restrict__ slots, int32_t n,
                                                     const float *__restrict__ x, const float *__restrict__ y,
                                                     const float *__restrict__ z, const float *__restrict__ m,
-                                                    float4 *__restrict__ sorted, const uint32_t *__restrict__ fail)
+                                                    float4 *__restrict__ sorted, const uint32_t *__restrict__ fail,
+                                                    BrickOrder O)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // When ordering the gather's bricks, workgroup 0 places them (the second
+    // phase) beside the ordering of the particles (one workgroup later).
+    uint32_t block = blockIdx.x;
+    if (O.order) {
+        if (block == 0u) {
+            order_bricks_place(O);
+            return;
+        }
+        --block;
+    }
+    const int64_t i = (int64_t)block * blockDim.x + threadIdx.x;
     if (i >= n || *fail) return;
     const uint32_t c = cid[i];
     if (c == 0xffffffffu) return;
@@ -978,6 +1017,7 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     // the one-pass scan (cleared with the counter by scan_reset) or the tile
     // sums of the three-pass one.
     uint32_t *fail = scan_fail_word(scan);
+    const BrickOrder O{bwork, nbricks, bwork && order ? 1 : 0};
     const int32_t ntiles = scan_tiles(cg.ncells);
     const bool onepass = ntiles <= SCAN_ONEPASS_TILES;
     bool first = true;
@@ -996,11 +1036,11 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     if (want_mmax)
         hipExtLaunchKernelGGL(k_cell_count<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1, fail, nullptr, 0, 0);
+                              count + cg.ncells + 1, fail, BrickOrder{nullptr, 0, 0});
     else
         hipExtLaunchKernelGGL(k_cell_count<false>, dim3(blocks_for(n, 256) + (bwork ? 1 : 0)), dim3(256), 0, s,
                               first ? t.start : nullptr, nullptr, 0, x, y, z, m, n, cg, cid, lrank, count,
-                              count + cg.ncells + 1, fail, bwork, nbricks, order ? 1 : 0);
+                              count + cg.ncells + 1, fail, O);
     if (onepass) {
         hipLaunchKernelGGL(k_scan_onepass, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, s, count, cg.ncells, ntiles,
                            (uint32_t *)scan, (uint64_t *)((char *)scan + SCAN_TAG_OFFSET), *scan_base, start,
@@ -1017,13 +1057,13 @@ hipError_t launch_cell_list(const float *x, const float *y, const float *z, cons
     }
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, s, cid, lrank, n, start, slots,
                        fail);
-    hipExtLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256)), dim3(256), 0, s, nullptr, t.stop, 0, cid, start,
-                          slots, n, x, y, z, m, sorted, fail);
+    hipExtLaunchKernelGGL(k_cell_order, dim3(blocks_for(n, 256) + (O.order ? 1 : 0)), dim3(256), 0, s, nullptr,
+                          t.stop, 0, cid, start, slots, n, x, y, z, m, sorted, fail, O);
     return hipGetLastError();
 }
 
 // bwork (optional): receives each brick's candidate count (and their largest
-// at bwork[2 nbricks], which the cell-count kernel cleared); border
+// at bwork[2 nbricks], which the cell-count launch cleared); border
 // (optional): the dispatch order of the bricks.
 hipError_t launch_splat(const SplatParams &P, const uint32_t *start, const float4 *sorted, float *dn,
                         const uint32_t *fail, uint32_t *bwork, const uint32_t *border, hipStream_t s,
